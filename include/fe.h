@@ -1,0 +1,190 @@
+/*
+ * fe.h -- C ABI of the MI355X frequent-episode counting library (libfe.so).
+ *
+ * The library counts non-overlapped occurrences of serial episodes with
+ * inter-event delay constraints over one time-ordered event stream, the
+ * problem of Sec. 2 of Cao et al., "Towards Chip-on-Chip Neuroscience: Fast
+ * Mining of Frequent Episodes Using Graphics Processors":
+ *
+ *   - an event stream is n events (E_i, t_i) with t_i <= t_(i+1) (Sec. 2,
+ *     first definition); here E_i is an int32 event type (a neuron id) in
+ *     [0, num_types) and t_i an int32 tick in [0, 2^30);
+ *   - a serial episode is an ordered tuple of N event types with one delay
+ *     interval (lo_k, hi_k] per hop, k = 1..N-1 (Sec. 2, second definition
+ *     and the inter-event constraint inequalities); types may repeat;
+ *   - its count is the size of the largest set of non-overlapped
+ *     occurrences (Sec. 2, "frequency of episodes"), computed by the serial
+ *     state machine of Algorithm 1 (Sec. 5.1);
+ *   - the relaxed count drops the lower bounds (Sec. 5.3.1, Algorithm 3): a
+ *     hop is satisfied by 0 <= gap <= hi_k; it is an upper bound on the
+ *     count (Theorem of Sec. 5.3.2);
+ *   - Problem 1 (Sec. 2): every episode with hops drawn from an interval set
+ *     I whose count is >= theta, mined level by level (Sec. 5 intro).
+ *
+ * Conventions for every call
+ *   - Return value: FE_OK (0) or a positive fe_status code.  Host-checkable
+ *     argument errors return at once and enqueue nothing.
+ *   - Pointers named "device" are HIP device pointers (e.g. torch CUDA
+ *     tensors' data_ptr()).  The caller owns them and keeps them valid
+ *     until the enqueued work has finished (fe_sync, or a synchronisation
+ *     of the context's stream).
+ *   - Work is enqueued on the context's stream.  Calls that need a size
+ *     known only on the device (candidate grouping, survivor counts, mining
+ *     levels) synchronise that stream internally before returning; they say
+ *     so below.
+ *   - Stream checks (sortedness, id and tick ranges) and candidate checks
+ *     run on the device.  A violation makes the call return FE_EUNSORTED,
+ *     FE_ERANGE or FE_EINVAL; no output is written in that case.
+ *   - The library owns its workspace (grown on demand, freed by
+ *     fe_destroy).  One context must not be used from two host threads at
+ *     once.
+ *
+ * Candidate table (device, row-major, int32):
+ *   types[M * nmax]       E_(1..N) of candidate m in types[m*nmax + 0..N-1],
+ *                         the rest unused;
+ *   len[M]                N of candidate m, 1 <= N <= nmax <= 8;
+ *   lo[M * (nmax-1)]      lo_k of hop k in lo[m*(nmax-1) + k], k < N-1;
+ *   hi[M * (nmax-1)]      hi_k likewise.  0 <= lo_k < hi_k < 2^30 and
+ *                         sum_k hi_k < 2^30.
+ *   For FE_EXACT, each hop must also satisfy hi/(hi-lo+1) < 8 (integer
+ *   division), which bounds the live state of Algorithm 1's lists; every
+ *   interval with lo <= 0.75*hi meets it (e.g. (0,5], (5,10], (10,15],
+ *   (10,20] ms).  A hop outside it is rejected with FE_EINVAL.
+ */
+#ifndef FE_H
+#define FE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fe_status {
+    FE_OK = 0,
+    FE_EINVAL = 1,    /* bad argument or candidate                          */
+    FE_ENOMEM = 2,    /* device or host allocation failed                   */
+    FE_EDEVICE = 3,   /* a HIP runtime call failed                          */
+    FE_EUNSORTED = 4, /* stream ticks decrease somewhere                    */
+    FE_ERANGE = 5,    /* an id outside [0,num_types) or tick outside [0,2^30) */
+    FE_EBUSY = 6,     /* server request not finished yet                    */
+    FE_EINTERNAL = 7  /* an internal invariant failed (a library bug)       */
+} fe_status;
+
+typedef enum fe_mode {
+    FE_EXACT = 0,  /* Algorithm 1: hop constraint lo < gap <= hi            */
+    FE_RELAXED = 1 /* Algorithm 3: hop constraint 0 <= gap <= hi (lo unused) */
+} fe_mode;
+
+/* Tunables for fe_set_param. */
+typedef enum fe_param {
+    FE_PARAM_SEGMENTS = 0,   /* MapConcatenate segment count P; 0 = automatic  */
+    FE_PARAM_TARGET_WAVES = 1, /* waves the automatic P aims for per launch    */
+    FE_PARAM_MIN_SEG_EVENTS = 2, /* smallest segment the automatic P allows   */
+    FE_PARAM_CONCAT_TREE = 3 /* 1 = wave-shuffle tree Concatenate when P >= 16,
+                                0 = per-candidate sequential walk              */
+} fe_param;
+
+typedef struct fe_ctx fe_ctx;
+
+/* Create a context on HIP device `device`.  `hip_stream` is the
+ * hipStream_t all work is enqueued on (NULL: the device's null stream,
+ * which is also what torch reports for its default stream). */
+int fe_create(int device, void *hip_stream, fe_ctx **out);
+
+/* Synchronise, free all workspace and the context. */
+int fe_destroy(fe_ctx *ctx);
+
+/* Message for the last error of this context (static storage of ctx). */
+const char *fe_last_error(const fe_ctx *ctx);
+
+/* Wait for the context's stream; return the first error detected on the
+ * device since the last fe_sync (and clear it), else FE_OK. */
+int fe_sync(fe_ctx *ctx);
+
+/* Set a tunable (fe_param).  Values < 0 are rejected. */
+int fe_set_param(fe_ctx *ctx, int param, int64_t value);
+int fe_get_param(const fe_ctx *ctx, int param, int64_t *value);
+
+/* Check a stream (device ids[n], ticks[n]) on the device: ticks
+ * non-decreasing, 0 <= tick < 2^30, 0 <= id < num_types.  Synchronises;
+ * returns FE_OK, FE_EUNSORTED or FE_ERANGE. */
+int fe_validate(fe_ctx *ctx, const int32_t *ids, const int32_t *ticks,
+                int64_t n, int32_t num_types);
+
+/* Count every candidate over the stream (Algorithm 1 for FE_EXACT,
+ * Algorithm 3 for FE_RELAXED), by MapConcatenate over P index segments
+ * (Sec. 5.2.2) with exact segment stitching.  counts_out: device int32[M],
+ * in candidate order.  Synchronises once (candidate grouping). */
+int fe_count(fe_ctx *ctx, const int32_t *ids, const int32_t *ticks, int64_t n,
+             int32_t num_types, const int32_t *types, const int32_t *len,
+             const int32_t *lo, const int32_t *hi, int32_t M, int32_t nmax,
+             int mode, int32_t *counts_out);
+
+/* Two-pass elimination, Algorithm 4 (Sec. 5.3.2): upper_out[m] = relaxed
+ * count; candidates with upper < theta are dropped (exact_out[m] = -1);
+ * exact_out[m] = exact count for the others.  *n_survivors_out (device
+ * int32) receives the number kept.  All outputs are device pointers.
+ * Synchronises (grouping of each pass). */
+int fe_count_two_pass(fe_ctx *ctx, const int32_t *ids, const int32_t *ticks,
+                      int64_t n, int32_t num_types, const int32_t *types,
+                      const int32_t *len, const int32_t *lo,
+                      const int32_t *hi, int32_t M, int32_t nmax,
+                      int32_t theta, int32_t *upper_out, int32_t *exact_out,
+                      int32_t *n_survivors_out);
+
+/* ---------------------------------------------------------------- mining */
+
+typedef struct fe_level {
+    int32_t level;        /* episode size N                                 */
+    int64_t n_candidates; /* candidates counted at this level               */
+    int64_t n_survivors;  /* candidates kept by the relaxed pass            */
+    int64_t n_frequent;   /* candidates whose exact count >= theta          */
+    int32_t *types;       /* [n_frequent * level] frequent episodes, sorted  */
+    int32_t *lo;          /* [n_frequent * (level-1)]                       */
+    int32_t *hi;          /* [n_frequent * (level-1)]                       */
+    int32_t *upper;       /* [n_frequent] relaxed counts                    */
+    int32_t *exact;       /* [n_frequent] exact counts                      */
+    double gen_ms;        /* host candidate generation time                 */
+    double count_ms;      /* device counting time (both passes)             */
+} fe_level;
+
+typedef struct fe_result {
+    int32_t n_levels;
+    fe_level *levels;     /* levels[0] is level 1 */
+} fe_result;
+
+/* Problem 1 (Sec. 2) by level-wise mining.  Level 1 counts each event type
+ * (a 1-node episode occurs at every event of its type); level 2 takes every
+ * ordered pair of frequent types (repeats allowed) times every interval of
+ * I; level l >= 3 joins two frequent (l-1)-node episodes whose overlapping
+ * l-2 nodes and intervals agree.  Every level is counted with Algorithm 4
+ * on the device; generation runs on the host (Sec. 5 intro).  Stops after
+ * max_level or at the first level with no frequent episode.  ids, ticks:
+ * device; iv_lo, iv_hi: host int32[n_iv] (the set I, in ticks).
+ * *out is allocated by the library; free it with fe_result_free.
+ * Synchronises. */
+int fe_mine(fe_ctx *ctx, const int32_t *ids, const int32_t *ticks, int64_t n,
+            int32_t num_types, const int32_t *iv_lo, const int32_t *iv_hi,
+            int32_t n_iv, int32_t theta, int32_t max_level, fe_result **out);
+
+void fe_result_free(fe_result *res);
+
+/* Per-call statistics of the last fe_count / fe_count_two_pass / fe_mine
+ * call on this context (host memory owned by ctx). */
+typedef struct fe_stats {
+    int64_t map_launches;   /* Map kernel launches                          */
+    int64_t segments_max;   /* largest P used                               */
+    int64_t fallback_cands; /* candidates recounted over the whole stream
+                               because a look-back held too many slots      */
+    double last_call_ms;    /* host wall time of the last call              */
+} fe_stats;
+
+int fe_get_stats(const fe_ctx *ctx, fe_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FE_H */

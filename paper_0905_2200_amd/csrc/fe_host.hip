@@ -1,0 +1,776 @@
+// fe_host.hip -- host runtime behind include/fe.h: context, workspace,
+// candidate grouping, launch planning, two-pass elimination and the
+// level-wise mining driver.
+#include "fe.h"
+#include "fe_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace fe;
+
+namespace {
+
+struct Buf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+}  // namespace
+
+struct fe_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    int64_t param[4] = {0, 4096, 1024, 1};
+    fe_stats stats{};
+    // workspace
+    Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small;
+    Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn;
+    int *host = nullptr;  // pinned host staging for small readbacks
+    size_t host_cap = 0;
+};
+
+namespace {
+
+int fail(fe_ctx *c, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(fe_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(c, x)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess)                                                          \
+            return fail((c), FE_EDEVICE, "%s failed: %s", #x, hipGetErrorString(e_));  \
+    } while (0)
+
+int ensure(fe_ctx *c, Buf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 4;
+    if (b.cap >= bytes) return FE_OK;
+    if (b.p) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        if (hipMalloc(&b.p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            b.p = nullptr;
+            return fail(c, FE_ENOMEM, "device allocation of %zu bytes failed", bytes);
+        }
+        want = bytes;
+    }
+    b.cap = want;
+    return FE_OK;
+}
+
+int ensure_host(fe_ctx *c, size_t ints)
+{
+    if (c->host_cap >= ints) return FE_OK;
+    if (c->host) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipHostFree(c->host));
+        c->host = nullptr;
+    }
+    if (hipHostMalloc((void **)&c->host, ints * sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        c->host = nullptr;
+        c->host_cap = 0;
+        return fail(c, FE_ENOMEM, "pinned host allocation failed");
+    }
+    c->host_cap = ints;
+    return FE_OK;
+}
+
+template <class T> T *P(Buf &b) { return (T *)b.p; }
+
+int status_code(int bits)
+{
+    if (bits & ST_BADCAND) return FE_EINVAL;
+    if (bits & ST_RANGE) return FE_ERANGE;
+    if (bits & ST_UNSORTED) return FE_EUNSORTED;
+    if (bits & ST_INTERNAL) return FE_EINTERNAL;
+    return FE_OK;
+}
+
+const char *status_text(int bits)
+{
+    if (bits & ST_BADCAND)
+        return "invalid candidate (N outside [1,nmax], type outside [0,num_types), "
+               "lo<0, lo>=hi, hi or sum(hi) >= 2^30, or hi/(hi-lo+1) >= 8 for FE_EXACT)";
+    if (bits & ST_RANGE) return "event id outside [0,num_types) or tick outside [0,2^30)";
+    if (bits & ST_UNSORTED) return "event ticks are not non-decreasing";
+    if (bits & ST_INTERNAL) return "internal invariant failed";
+    return "ok";
+}
+
+struct CandIn {
+    const int *types, *len, *lo, *hi;
+    int nmax;
+};
+
+struct StreamInfo {
+    int n;
+    int span;  // ticks[n-1] - ticks[0] + 1
+};
+
+// Segment count P for a group of `tiles` tiles: enough waves to fill the
+// GPU, but segments long against the look-back (about n*W/span events).
+int choose_P(const fe_ctx *c, int tiles, const StreamInfo &si, int Wmax)
+{
+    const int n = si.n;
+    if (n <= 1) return 1;
+    if (c->param[FE_PARAM_SEGMENTS] > 0)
+        return (int)std::min<int64_t>(c->param[FE_PARAM_SEGMENTS], n);
+    const int64_t target = c->param[FE_PARAM_TARGET_WAVES];
+    int64_t P = (target + tiles - 1) / std::max(tiles, 1);
+    const double lb = (double)n * (double)Wmax / std::max(si.span, 1);
+    const int64_t minseg = std::max<int64_t>(c->param[FE_PARAM_MIN_SEG_EVENTS],
+                                             (int64_t)(8.0 * lb) + 64);
+    P = std::min<int64_t>(P, std::max<int64_t>(1, n / minseg));
+    P = std::min<int64_t>(P, 4096);
+    return (int)std::max<int64_t>(P, 1);
+}
+
+// One counting pass (relaxed or exact) over candidates cin (optionally the
+// subset sel[0..*nsel) of them), writing out[m] for every counted m.
+int run_pass(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, int num_types,
+             const CandIn &cin, const int *sel, const int *nsel, int M, bool exact, int *out)
+{
+    hipStream_t s = c->stream;
+    int rc;
+    if ((rc = ensure(c, c->keys, (size_t)M * sizeof(int)))) return rc;
+    if ((rc = ensure(c, c->hist, 2 * NKEYS * sizeof(int)))) return rc;
+    if ((rc = ensure(c, c->fill, NKEYS * sizeof(int)))) return rc;
+    int *hist = P<int>(c->hist);
+    launch_fill(hist, 0, 2 * NKEYS, s);
+    launch_fill(P<int>(c->fill), 0, NKEYS, s);
+    launch_prep_count(cin.types, cin.len, cin.lo, cin.hi, cin.nmax, sel, nsel, M, num_types,
+                      exact ? 1 : 0, P<int>(c->keys), hist, P<int>(c->status), s);
+    if ((rc = ensure_host(c, 2 * NKEYS + 1))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->host, hist, NKEYS * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->host + NKEYS + 1, hist + NKEYS, NKEYS * sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->host + NKEYS, P<int>(c->status), sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipGetLastError());
+    const int bits = c->host[NKEYS];
+    if (bits) {
+        launch_fill(P<int>(c->status), 0, 1, s);
+        return fail(c, status_code(bits), "%s", status_text(bits));
+    }
+    int cnt[NKEYS], wmax[NKEYS];
+    std::memcpy(cnt, c->host, sizeof cnt);
+    std::memcpy(wmax, c->host + NKEYS + 1, sizeof wmax);
+
+    Layout lay;
+    int tiles_total = 0;
+    int64_t rec_total = 0;
+    for (int k = 0; k < NKEYS; ++k) {
+        const int N = k / NDCLS + 1;
+        const int t = (cnt[k] + WAVE - 1) / WAVE;
+        lay.tile_base[k] = tiles_total;
+        lay.rec_base[k] = (int)rec_total;
+        tiles_total += t;
+        rec_total += (int64_t)t * rec_ints(N);
+    }
+    if (rec_total >= (int64_t)1 << 31)
+        return fail(c, FE_EINVAL, "candidate table too large (%lld ints)", (long long)rec_total);
+    if (tiles_total == 0) return FE_OK;
+    if ((rc = ensure(c, c->pk, (size_t)rec_total * sizeof(int)))) return rc;
+    if ((rc = ensure(c, c->orig, (size_t)tiles_total * WAVE * sizeof(int)))) return rc;
+    if ((rc = ensure(c, c->tileW, (size_t)tiles_total * sizeof(int)))) return rc;
+    launch_fill(P<int>(c->pk), -1, rec_total, s);
+    launch_fill(P<int>(c->orig), -1, (int64_t)tiles_total * WAVE, s);
+    launch_fill(P<int>(c->tileW), 0, tiles_total, s);
+    launch_prep_scatter(cin.types, cin.len, cin.lo, cin.hi, cin.nmax, sel, nsel, M,
+                        P<int>(c->keys), lay, P<int>(c->fill), P<int>(c->pk), P<int>(c->orig),
+                        P<int>(c->tileW), s);
+
+    for (int k = 0; k < NKEYS; ++k) {
+        if (!cnt[k]) continue;
+        const int N = k / NDCLS + 1, dcls = k % NDCLS;
+        const int tiles = (cnt[k] + WAVE - 1) / WAVE;
+        MapGroup g;
+        g.ids = ids;
+        g.ticks = ticks;
+        g.n = si.n;
+        g.pk = P<int>(c->pk) + lay.rec_base[k];
+        g.orig = P<int>(c->orig) + (int64_t)lay.tile_base[k] * WAVE;
+        g.out = out;
+        g.status = P<int>(c->status);
+        g.tiles = tiles;
+        g.lam = nullptr;
+        g.tbl = nullptr;
+        g.flags = nullptr;
+        g.P = choose_P(c, tiles, si, wmax[k]);
+        c->stats.map_launches++;
+        c->stats.segments_max = std::max<int64_t>(c->stats.segments_max, g.P);
+        if (g.P > 1) {
+            const int64_t lam_n = (int64_t)tiles * (g.P + 1);
+            const int64_t tbl_n = (int64_t)g.P * tiles * WAVE * KMAX;
+            if ((rc = ensure(c, c->lam, (size_t)lam_n * sizeof(int)))) return rc;
+            if ((rc = ensure(c, c->tbl, (size_t)tbl_n * sizeof(int2)))) return rc;
+            if ((rc = ensure(c, c->flags, (size_t)tiles * WAVE * sizeof(int)))) return rc;
+            g.lam = P<int>(c->lam);
+            g.tbl = P<int2>(c->tbl);
+            g.flags = P<int>(c->flags);
+            launch_fill(g.flags, 0, (int64_t)tiles * WAVE, s);
+            launch_plan(ticks, si.n, P<int>(c->tileW) + lay.tile_base[k], tiles, g.P, P<int>(c->lam), s);
+            launch_map(N, exact, dcls, g, s);
+            launch_concat(g, c->param[FE_PARAM_CONCAT_TREE] && g.P >= 16, s);
+            launch_fixup(N, exact, dcls, g, s);
+        } else {
+            launch_map(N, exact, dcls, g, s);
+        }
+        HIPCHK(c, hipGetLastError());
+    }
+    return FE_OK;
+}
+
+int check_common(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int64_t n,
+                 int32_t num_types)
+{
+    if (!c) return FE_EINVAL;
+    if (n < 0 || n >= ((int64_t)1 << 31) - 64) return fail(c, FE_EINVAL, "n out of range");
+    if (n > 0 && (!ids || !ticks)) return fail(c, FE_EINVAL, "null stream pointer");
+    if (num_types <= 0) return fail(c, FE_EINVAL, "num_types must be positive");
+    return FE_OK;
+}
+
+int check_cands(fe_ctx *c, const int32_t *types, const int32_t *len, const int32_t *lo,
+                const int32_t *hi, int32_t M, int32_t nmax)
+{
+    if (M < 0) return fail(c, FE_EINVAL, "M < 0");
+    if (nmax < 1 || nmax > NMAX) return fail(c, FE_EINVAL, "nmax outside [1,8]");
+    if (M > 0 && (!types || !len || (nmax > 1 && (!lo || !hi))))
+        return fail(c, FE_EINVAL, "null candidate pointer");
+    if ((int64_t)M * nmax >= ((int64_t)1 << 31)) return fail(c, FE_EINVAL, "M too large");
+    return FE_OK;
+}
+
+// Validate the stream and learn its tick span (synchronises).
+int stream_info(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int n, int num_types,
+                StreamInfo &si)
+{
+    int rc;
+    si.n = n;
+    si.span = 1;
+    if (n == 0) return FE_OK;
+    launch_validate(ids, ticks, n, num_types, P<int>(c->status), c->stream);
+    if ((rc = ensure_host(c, 4))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->host, ticks, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->host + 1, ticks + (n - 1), sizeof(int), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->host + 2, P<int>(c->status), sizeof(int),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int bits = c->host[2];
+    if (bits) {
+        launch_fill(P<int>(c->status), 0, 1, c->stream);
+        return fail(c, status_code(bits), "%s", status_text(bits));
+    }
+    si.span = std::max(1, c->host[1] - c->host[0] + 1);
+    return FE_OK;
+}
+
+int count_impl(fe_ctx *c, const int32_t *ids, const int32_t *ticks, const StreamInfo &si,
+               int32_t num_types, const CandIn &cin, int32_t M, int mode, int32_t *out)
+{
+    if (M == 0) return FE_OK;
+    if (si.n == 0) {
+        launch_fill(out, 0, M, c->stream);
+        return FE_OK;
+    }
+    return run_pass(c, ids, ticks, si, num_types, cin, nullptr, nullptr, M, mode == FE_EXACT,
+                    out);
+}
+
+int two_pass_impl(fe_ctx *c, const int32_t *ids, const int32_t *ticks, const StreamInfo &si,
+                  int32_t num_types, const CandIn &cin, int32_t M, int32_t theta,
+                  int32_t *upper, int32_t *exact, int32_t *nsurv_out)
+{
+    int rc;
+    hipStream_t s = c->stream;
+    if ((rc = ensure(c, c->nsel, sizeof(int)))) return rc;
+    launch_fill(P<int>(c->nsel), 0, 1, s);
+    if (M == 0) {
+        if (nsurv_out)
+            HIPCHK(c, hipMemcpyAsync(nsurv_out, P<int>(c->nsel), sizeof(int),
+                                     hipMemcpyDeviceToDevice, s));
+        return FE_OK;
+    }
+    if ((rc = count_impl(c, ids, ticks, si, num_types, cin, M, FE_RELAXED, upper))) return rc;
+    if ((rc = ensure(c, c->sel, (size_t)M * sizeof(int)))) return rc;
+    // empty stream: every count is 0, so kept candidates keep exact = 0
+    if (si.n == 0) launch_fill(exact, 0, M, s);
+    launch_compact(upper, M, theta, exact, P<int>(c->sel), P<int>(c->nsel), s);
+    if (si.n > 0 &&
+        (rc = run_pass(c, ids, ticks, si, num_types, cin, P<int>(c->sel), P<int>(c->nsel), M,
+                       true, exact)))
+        return rc;
+    if (nsurv_out)
+        HIPCHK(c, hipMemcpyAsync(nsurv_out, P<int>(c->nsel), sizeof(int), hipMemcpyDeviceToDevice,
+                                 s));
+    return FE_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" int fe_create(int device, void *hip_stream, fe_ctx **out)
+{
+    if (!out) return FE_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return FE_EDEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) return FE_EDEVICE;
+    fe_ctx *c = new (std::nothrow) fe_ctx();
+    if (!c) return FE_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;  // NULL: the device's null stream
+    c->own_stream = false;
+    if (ensure(c, c->status, sizeof(int)) || ensure_host(c, 64)) {
+        fe_destroy(c);
+        return FE_ENOMEM;
+    }
+    launch_fill(P<int>(c->status), 0, 1, c->stream);
+    *out = c;
+    return FE_OK;
+}
+
+extern "C" int fe_destroy(fe_ctx *c)
+{
+    if (!c) return FE_EINVAL;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    Buf *bufs[] = {&c->keys, &c->hist, &c->wmax, &c->fill, &c->pk,    &c->orig,  &c->tileW,
+                   &c->lam,  &c->tbl,  &c->flags, &c->sel, &c->nsel,  &c->status, &c->small,
+                   &c->mtypes, &c->mlen, &c->mlo, &c->mhi, &c->mup, &c->mex, &c->msel, &c->mn};
+    for (Buf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (c->host) (void)hipHostFree(c->host);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return FE_OK;
+}
+
+extern "C" const char *fe_last_error(const fe_ctx *c)
+{
+    return c ? c->err.c_str() : "null context";
+}
+
+extern "C" int fe_sync(fe_ctx *c)
+{
+    if (!c) return FE_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(c->host, P<int>(c->status), sizeof(int), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
+    const int bits = c->host[0];
+    if (bits) {
+        launch_fill(P<int>(c->status), 0, 1, c->stream);
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return fail(c, status_code(bits), "%s", status_text(bits));
+    }
+    return FE_OK;
+}
+
+extern "C" int fe_set_param(fe_ctx *c, int param, int64_t value)
+{
+    if (!c) return FE_EINVAL;
+    if (param < 0 || param > 3 || value < 0) return fail(c, FE_EINVAL, "bad parameter");
+    if (param == FE_PARAM_TARGET_WAVES && value == 0) return fail(c, FE_EINVAL, "bad parameter");
+    c->param[param] = value;
+    return FE_OK;
+}
+
+extern "C" int fe_get_param(const fe_ctx *c, int param, int64_t *value)
+{
+    if (!c || !value || param < 0 || param > 3) return FE_EINVAL;
+    *value = c->param[param];
+    return FE_OK;
+}
+
+extern "C" int fe_get_stats(const fe_ctx *c, fe_stats *out)
+{
+    if (!c || !out) return FE_EINVAL;
+    *out = c->stats;
+    return FE_OK;
+}
+
+extern "C" int fe_validate(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int64_t n,
+                           int32_t num_types)
+{
+    int rc;
+    if ((rc = check_common(c, ids, ticks, n, num_types))) return rc;
+    HIPCHK(c, hipSetDevice(c->device));
+    StreamInfo si;
+    return stream_info(c, ids, ticks, (int)n, num_types, si);
+}
+
+extern "C" int fe_count(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int64_t n,
+                        int32_t num_types, const int32_t *types, const int32_t *len,
+                        const int32_t *lo, const int32_t *hi, int32_t M, int32_t nmax, int mode,
+                        int32_t *counts_out)
+{
+    int rc;
+    const double t0 = now_ms();
+    if ((rc = check_common(c, ids, ticks, n, num_types))) return rc;
+    if ((rc = check_cands(c, types, len, lo, hi, M, nmax))) return rc;
+    if (mode != FE_EXACT && mode != FE_RELAXED) return fail(c, FE_EINVAL, "bad mode");
+    if (M > 0 && !counts_out) return fail(c, FE_EINVAL, "null output");
+    HIPCHK(c, hipSetDevice(c->device));
+    c->stats = fe_stats{};
+    StreamInfo si;
+    if ((rc = stream_info(c, ids, ticks, (int)n, num_types, si))) return rc;
+    CandIn cin{types, len, lo, hi, nmax};
+    rc = count_impl(c, ids, ticks, si, num_types, cin, M, mode, counts_out);
+    c->stats.last_call_ms = now_ms() - t0;
+    return rc;
+}
+
+extern "C" int fe_count_two_pass(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int64_t n,
+                                 int32_t num_types, const int32_t *types, const int32_t *len,
+                                 const int32_t *lo, const int32_t *hi, int32_t M, int32_t nmax,
+                                 int32_t theta, int32_t *upper_out, int32_t *exact_out,
+                                 int32_t *n_survivors_out)
+{
+    int rc;
+    const double t0 = now_ms();
+    if ((rc = check_common(c, ids, ticks, n, num_types))) return rc;
+    if ((rc = check_cands(c, types, len, lo, hi, M, nmax))) return rc;
+    if (M > 0 && (!upper_out || !exact_out)) return fail(c, FE_EINVAL, "null output");
+    HIPCHK(c, hipSetDevice(c->device));
+    c->stats = fe_stats{};
+    StreamInfo si;
+    if ((rc = stream_info(c, ids, ticks, (int)n, num_types, si))) return rc;
+    CandIn cin{types, len, lo, hi, nmax};
+    rc = two_pass_impl(c, ids, ticks, si, num_types, cin, M, theta, upper_out, exact_out,
+                       n_survivors_out);
+    c->stats.last_call_ms = now_ms() - t0;
+    return rc;
+}
+
+// ====================================================================== mining
+
+namespace {
+
+// An episode of size m is keyed by its interleaved tuple
+// (E1, lo1, hi1, E2, ..., lo_(m-1), hi_(m-1), E_m): 3m-2 ints.  The prefix
+// (first m-1 nodes) is the first 3m-5 ints, the suffix (last m-1 nodes)
+// the last 3m-5 ints.
+struct Episodes {
+    int m = 0;             // episode size
+    std::vector<int> key;  // [count * (3m-2)]
+    size_t count() const { return m ? key.size() / (3 * m - 2) : 0; }
+    const int *at(size_t i) const { return key.data() + i * (3 * m - 2); }
+};
+
+void sort_episodes(Episodes &E, std::vector<int> *vals_a, std::vector<int> *vals_b)
+{
+    const int w = 3 * E.m - 2;
+    const size_t F = E.count();
+    std::vector<size_t> idx(F);
+    for (size_t i = 0; i < F; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+        return std::lexicographical_compare(E.at(a), E.at(a) + w, E.at(b), E.at(b) + w);
+    });
+    std::vector<int> k2(E.key.size());
+    std::vector<int> a2(vals_a ? F : 0), b2(vals_b ? F : 0);
+    for (size_t i = 0; i < F; ++i) {
+        std::memcpy(k2.data() + i * w, E.at(idx[i]), w * sizeof(int));
+        if (vals_a) a2[i] = (*vals_a)[idx[i]];
+        if (vals_b) b2[i] = (*vals_b)[idx[i]];
+    }
+    E.key.swap(k2);
+    if (vals_a) vals_a->swap(a2);
+    if (vals_b) vals_b->swap(b2);
+}
+
+// Level 2: every ordered pair of frequent types (repeats allowed) times
+// every interval of I.
+void gen_level2(const std::vector<int> &F1, const std::vector<int> &ilo,
+                const std::vector<int> &ihi, Episodes &out)
+{
+    out.m = 2;
+    out.key.clear();
+    out.key.reserve(F1.size() * F1.size() * ilo.size() * 4);
+    for (int a : F1)
+        for (int b : F1)
+            for (size_t k = 0; k < ilo.size(); ++k) {
+                out.key.push_back(a);
+                out.key.push_back(ilo[k]);
+                out.key.push_back(ihi[k]);
+                out.key.push_back(b);
+            }
+}
+
+// Level m+1 from the sorted frequent set of size m: alpha joined with every
+// beta whose first m-1 nodes and intervals equal alpha's last m-1.
+void gen_join(const Episodes &F, Episodes &out)
+{
+    const int m = F.m, w = 3 * m - 2, ov = 3 * m - 5;
+    out.m = m + 1;
+    out.key.clear();
+    const size_t cnt = F.count();
+    std::vector<size_t> order(cnt);
+    for (size_t i = 0; i < cnt; ++i) order[i] = i;
+    auto pre_less = [&](size_t b, const int *key) {
+        return std::lexicographical_compare(F.at(b), F.at(b) + ov, key, key + ov);
+    };
+    auto key_less = [&](const int *key, size_t b) {
+        return std::lexicographical_compare(key, key + ov, F.at(b), F.at(b) + ov);
+    };
+    for (size_t a = 0; a < cnt; ++a) {
+        const int *suf = F.at(a) + 3;
+        auto lo_it = std::lower_bound(order.begin(), order.end(), suf, pre_less);
+        auto hi_it = std::upper_bound(lo_it, order.end(), suf, key_less);
+        for (auto it = lo_it; it != hi_it; ++it) {
+            const int *al = F.at(a), *be = F.at(*it);
+            out.key.insert(out.key.end(), al, al + 3);
+            out.key.insert(out.key.end(), be, be + w);
+        }
+    }
+}
+
+struct LevelOut {
+    int level;
+    int64_t ncand, nsurv, nfreq;
+    std::vector<int> types, lo, hi, upper, exact;
+    double gen_ms, count_ms;
+};
+
+}  // namespace
+
+extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int64_t n,
+                       int32_t num_types, const int32_t *iv_lo, const int32_t *iv_hi, int32_t n_iv,
+                       int32_t theta, int32_t max_level, fe_result **out)
+{
+    int rc;
+    const double t_call = now_ms();
+    if (!out) return fail(c, FE_EINVAL, "null result pointer");
+    *out = nullptr;
+    if ((rc = check_common(c, ids, ticks, n, num_types))) return rc;
+    if (max_level < 1 || max_level > NMAX) return fail(c, FE_EINVAL, "max_level outside [1,8]");
+    if (n_iv < 0 || (n_iv > 0 && (!iv_lo || !iv_hi)))
+        return fail(c, FE_EINVAL, "bad interval set");
+    std::vector<int> ilo(iv_lo, iv_lo + n_iv), ihi(iv_hi, iv_hi + n_iv);
+    for (int k = 0; k < n_iv; ++k) {
+        const int l = ilo[k], h = ihi[k];
+        if (l < 0 || l >= h || h >= TICK_LIMIT || h / (h - l + 1) >= 8)
+            return fail(c, FE_EINVAL, "interval %d = (%d,%d] invalid", k, l, h);
+        if ((int64_t)h * max_level >= TICK_LIMIT)
+            return fail(c, FE_EINVAL, "interval %d too wide for max_level", k);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    c->stats = fe_stats{};
+    hipStream_t s = c->stream;
+    StreamInfo si;
+    if ((rc = stream_info(c, ids, ticks, (int)n, num_types, si))) return rc;
+
+    std::vector<LevelOut> levels;
+    // level 1: a one-node episode occurs at every event of its type
+    double t0 = now_ms();
+    if ((rc = ensure(c, c->mn, (size_t)num_types * sizeof(int)))) return rc;
+    launch_fill(P<int>(c->mn), 0, num_types, s);
+    launch_histogram(ids, (int)n, num_types, P<int>(c->mn), s);
+    std::vector<int> hist(num_types);
+    HIPCHK(c, hipMemcpyAsync(hist.data(), P<int>(c->mn), num_types * sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    {
+        LevelOut L1;
+        L1.level = 1;
+        L1.ncand = num_types;
+        L1.nsurv = num_types;
+        for (int e = 0; e < num_types; ++e)
+            if (hist[e] >= theta) {
+                L1.types.push_back(e);
+                L1.upper.push_back(hist[e]);
+                L1.exact.push_back(hist[e]);
+            }
+        L1.nfreq = (int64_t)L1.types.size();
+        L1.gen_ms = 0;
+        L1.count_ms = now_ms() - t0;
+        levels.push_back(std::move(L1));
+    }
+    Episodes F;
+    F.m = 1;
+    for (int e : levels[0].types) F.key.push_back(e);
+
+    for (int level = 2; level <= max_level && F.count() > 0 && n_iv > 0; ++level) {
+        t0 = now_ms();
+        Episodes C;
+        if (level == 2) gen_level2(levels[0].types, ilo, ihi, C);
+        else gen_join(F, C);
+        const size_t M = C.count();
+        if (M == 0) break;
+        if (M >= (size_t)1 << 31 || M * level >= (size_t)1 << 31)
+            return fail(c, FE_ENOMEM, "level %d has too many candidates (%zu)", level, M);
+        // device candidate table in the fe_count layout
+        const int w = 3 * level - 2;
+        std::vector<int> ty(M * level), lo(M * (level - 1)), hi(M * (level - 1));
+        for (size_t i = 0; i < M; ++i) {
+            const int *k = C.at(i);
+            for (int j = 0; j < level; ++j) ty[i * level + j] = k[3 * j];
+            for (int j = 0; j < level - 1; ++j) {
+                lo[i * (level - 1) + j] = k[3 * j + 1];
+                hi[i * (level - 1) + j] = k[3 * j + 2];
+            }
+        }
+        (void)w;
+        const double gen_ms = now_ms() - t0;
+        t0 = now_ms();
+        if ((rc = ensure(c, c->mtypes, ty.size() * sizeof(int)))) return rc;
+        if ((rc = ensure(c, c->mlen, M * sizeof(int)))) return rc;
+        if ((rc = ensure(c, c->mlo, lo.size() * sizeof(int)))) return rc;
+        if ((rc = ensure(c, c->mhi, hi.size() * sizeof(int)))) return rc;
+        if ((rc = ensure(c, c->mup, 2 * M * sizeof(int)))) return rc;
+        if ((rc = ensure(c, c->mex, 2 * M * sizeof(int)))) return rc;
+        if ((rc = ensure(c, c->msel, M * sizeof(int)))) return rc;
+        if ((rc = ensure(c, c->mn, 4 * sizeof(int)))) return rc;
+        HIPCHK(c, hipMemcpyAsync(P<int>(c->mtypes), ty.data(), ty.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(P<int>(c->mlo), lo.data(), lo.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(P<int>(c->mhi), hi.data(), hi.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, s));
+        launch_fill(P<int>(c->mlen), level, (int64_t)M, s);
+        int *up = P<int>(c->mup), *ex = P<int>(c->mex);
+        CandIn cin{P<int>(c->mtypes), P<int>(c->mlen), P<int>(c->mlo), P<int>(c->mhi), level};
+        if ((rc = two_pass_impl(c, ids, ticks, si, num_types, cin, (int)M, theta, up, ex,
+                                P<int>(c->mn) + 1)))
+            return rc;
+        // frequent = exact >= theta
+        launch_fill(P<int>(c->mn), 0, 1, s);
+        launch_compact(ex, (int)M, theta, nullptr, P<int>(c->msel), P<int>(c->mn), s);
+        launch_gather2(up, ex, P<int>(c->msel), P<int>(c->mn), (int)M, up + M, ex + M, s);
+        int cnts[2];
+        HIPCHK(c, hipMemcpyAsync(cnts, P<int>(c->mn), 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        const int nf = cnts[0];
+        std::vector<int> fsel(nf), fup(nf), fex(nf);
+        if (nf > 0) {
+            HIPCHK(c, hipMemcpyAsync(fsel.data(), P<int>(c->msel), nf * sizeof(int),
+                                     hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpyAsync(fup.data(), up + M, nf * sizeof(int), hipMemcpyDeviceToHost,
+                                     s));
+            HIPCHK(c, hipMemcpyAsync(fex.data(), ex + M, nf * sizeof(int), hipMemcpyDeviceToHost,
+                                     s));
+            HIPCHK(c, hipStreamSynchronize(s));
+        }
+        Episodes NF;
+        NF.m = level;
+        NF.key.resize((size_t)nf * (3 * level - 2));
+        for (int i = 0; i < nf; ++i)
+            std::memcpy(NF.key.data() + (size_t)i * (3 * level - 2), C.at(fsel[i]),
+                        (3 * level - 2) * sizeof(int));
+        sort_episodes(NF, &fup, &fex);
+        LevelOut Lv;
+        Lv.level = level;
+        Lv.ncand = (int64_t)M;
+        Lv.nsurv = cnts[1];
+        Lv.nfreq = nf;
+        Lv.types.resize((size_t)nf * level);
+        Lv.lo.resize((size_t)nf * (level - 1));
+        Lv.hi.resize((size_t)nf * (level - 1));
+        for (int i = 0; i < nf; ++i) {
+            const int *k = NF.at(i);
+            for (int j = 0; j < level; ++j) Lv.types[(size_t)i * level + j] = k[3 * j];
+            for (int j = 0; j < level - 1; ++j) {
+                Lv.lo[(size_t)i * (level - 1) + j] = k[3 * j + 1];
+                Lv.hi[(size_t)i * (level - 1) + j] = k[3 * j + 2];
+            }
+        }
+        Lv.upper = fup;
+        Lv.exact = fex;
+        Lv.gen_ms = gen_ms;
+        Lv.count_ms = now_ms() - t0;
+        levels.push_back(std::move(Lv));
+        F.m = level;
+        F.key.swap(NF.key);
+    }
+
+    fe_result *r = (fe_result *)std::calloc(1, sizeof(fe_result));
+    if (!r) return fail(c, FE_ENOMEM, "host allocation failed");
+    r->n_levels = (int)levels.size();
+    r->levels = (fe_level *)std::calloc(levels.size(), sizeof(fe_level));
+    if (!r->levels) {
+        std::free(r);
+        return fail(c, FE_ENOMEM, "host allocation failed");
+    }
+    auto dup = [](const std::vector<int> &v) {
+        int *p = (int *)std::malloc(std::max<size_t>(v.size(), 1) * sizeof(int));
+        if (p && !v.empty()) std::memcpy(p, v.data(), v.size() * sizeof(int));
+        return p;
+    };
+    for (size_t i = 0; i < levels.size(); ++i) {
+        fe_level &d = r->levels[i];
+        const LevelOut &L = levels[i];
+        d.level = L.level;
+        d.n_candidates = L.ncand;
+        d.n_survivors = L.nsurv;
+        d.n_frequent = L.nfreq;
+        d.types = dup(L.types);
+        d.lo = dup(L.lo);
+        d.hi = dup(L.hi);
+        d.upper = dup(L.upper);
+        d.exact = dup(L.exact);
+        d.gen_ms = L.gen_ms;
+        d.count_ms = L.count_ms;
+    }
+    *out = r;
+    c->stats.last_call_ms = now_ms() - t_call;
+    return FE_OK;
+}
+
+extern "C" void fe_result_free(fe_result *r)
+{
+    if (!r) return;
+    for (int i = 0; i < r->n_levels; ++i) {
+        std::free(r->levels[i].types);
+        std::free(r->levels[i].lo);
+        std::free(r->levels[i].hi);
+        std::free(r->levels[i].upper);
+        std::free(r->levels[i].exact);
+    }
+    std::free(r->levels);
+    std::free(r);
+}

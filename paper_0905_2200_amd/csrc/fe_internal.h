@@ -1,0 +1,74 @@
+// fe_internal.h -- shared between the host runtime (fe_host.hip) and the
+// device kernels (fe_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fe {
+
+constexpr int WAVE = 64;
+constexpr int NMAX = 8;          // largest episode size
+constexpr int KMAX = 4;          // slot-table entries kept per (candidate, segment)
+constexpr int NDCLS = 4;         // list-depth classes of the exact machine: 1,2,4,8 windows
+constexpr int NKEYS = NMAX * NDCLS;
+constexpr int TICK_LIMIT = 1 << 30;
+constexpr int WPB = 4;           // waves per block in the Map kernels
+
+// device status bits
+constexpr int ST_UNSORTED = 1;
+constexpr int ST_RANGE = 2;
+constexpr int ST_BADCAND = 4;
+constexpr int ST_INTERNAL = 8;
+
+inline constexpr int dcls_depth(int c) { return 1 << c; }
+// ints in one packed tile record: types[N][64], lo[N-1][64], hi[N-1][64]
+inline constexpr int rec_ints(int N) { return (3 * N - 2) * WAVE; }
+
+// Per-key placement of candidate groups in the packed table.
+struct Layout {
+    int tile_base[NKEYS];  // first tile of the group
+    int rec_base[NKEYS];   // int offset of the group's first record
+};
+
+// Everything a Map launch of one group needs.
+struct MapGroup {
+    const int *ids, *ticks;
+    int n;
+    const int *pk;     // group's first record
+    const int *orig;   // [tiles*64] original candidate index, -1 = padding
+    const int *lam;    // [tiles*(P+1)] look-back starts (P > 1)
+    int2 *tbl;         // [P][tiles*64][KMAX] slot tables (P > 1)
+    int *flags;        // [tiles*64] slot overflow flags (P > 1)
+    int *out;          // [M] per original candidate
+    int *status;
+    int tiles;
+    int P;
+};
+
+// launchers (fe_kernels.hip)
+void launch_fill(int *p, int v, int64_t n, hipStream_t s);
+void launch_validate(const int *ids, const int *ticks, int n, int num_types,
+                     int *status, hipStream_t s);
+void launch_prep_count(const int *types, const int *len, const int *lo,
+                       const int *hi, int nmax, const int *sel,
+                       const int *nsel, int M, int num_types, int exact,
+                       int *keys, int *hist, int *status, hipStream_t s);
+void launch_prep_scatter(const int *types, const int *len, const int *lo,
+                         const int *hi, int nmax, const int *sel,
+                         const int *nsel, int M, const int *keys,
+                         const Layout &lay, int *fill, int *pk, int *orig,
+                         int *tileW, hipStream_t s);
+void launch_plan(const int *ticks, int n, const int *tileW, int tiles, int P,
+                 int *lam, hipStream_t s);
+void launch_map(int N, bool exact, int dcls, const MapGroup &g, hipStream_t s);
+void launch_concat(const MapGroup &g, bool tree, hipStream_t s);
+void launch_fixup(int N, bool exact, int dcls, const MapGroup &g, hipStream_t s);
+void launch_compact(const int *vals, int M, int theta, int *pruned_out,
+                    int *sel, int *nsel, hipStream_t s);
+void launch_gather2(const int *a, const int *b, const int *sel, const int *nsel, int M,
+                    int *out_a, int *out_b, hipStream_t s);
+void launch_histogram(const int *ids, int n, int num_types, int *hist,
+                      hipStream_t s);
+
+}  // namespace fe

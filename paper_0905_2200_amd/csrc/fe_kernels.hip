@@ -1,0 +1,406 @@
+// fe_kernels.hip -- utility kernels (fill, stream validation, candidate
+// grouping, segment plan, Concatenate, elimination, level-1 histogram) and
+// the dispatch of the per-N Map kernels (fe_map.h, fe_map_n<N>.hip).
+#include "fe_internal.h"
+
+namespace fe {
+
+__device__ __forceinline__ int uniform_u(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ------------------------------------------------------------------ utilities
+__global__ void k_fill(int *p, int v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void launch_fill(int *p, int v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+}
+
+// ------------------------------------------------------------------ validate
+__global__ void k_validate(const int *__restrict__ ids, const int *__restrict__ ticks,
+                           int n, int num_types, int *status)
+{
+    int bits = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int e = ids[i], t = ticks[i];
+        if (e < 0 || e >= num_types || t < 0 || t >= TICK_LIMIT) bits |= ST_RANGE;
+        if (i > 0 && ticks[i - 1] > t) bits |= ST_UNSORTED;
+    }
+    if (bits) atomicOr(status, bits);
+}
+
+void launch_validate(const int *ids, const int *ticks, int n, int num_types, int *status,
+                     hipStream_t s)
+{
+    if (n <= 0) return;
+    int blocks = (n + 1023) / 1024;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_validate, dim3(blocks), dim3(256), 0, s, ids, ticks, n, num_types,
+                       status);
+}
+
+// ------------------------------------------------------------------ candidate grouping
+// Key of a candidate: (N-1)*NDCLS + depth class; -1 if the candidate is invalid.
+__device__ int cand_key(const int *types, const int *len, const int *lo, const int *hi,
+                        int nmax, int m, int num_types, int exact, int *W_out)
+{
+    const int N = len[m];
+    if (N < 1 || N > nmax) return -1;
+    const int64_t tb = (int64_t)m * nmax, ib = (int64_t)m * (nmax - 1);
+    for (int k = 0; k < N; ++k) {
+        const int t = types[tb + k];
+        if (t < 0 || t >= num_types) return -1;
+    }
+    int64_t W = 0;
+    int bound = 1;
+    for (int k = 0; k < N - 1; ++k) {
+        const int l = lo[ib + k], h = hi[ib + k];
+        if (l < 0 || l >= h || h >= TICK_LIMIT) return -1;
+        W += h;
+        const int b = h / (h - l + 1) + 1;
+        bound = b > bound ? b : bound;
+    }
+    if (W >= TICK_LIMIT) return -1;
+    int dc = 0;
+    if (exact) {
+        if (bound <= 1) dc = 0;
+        else if (bound <= 2) dc = 1;
+        else if (bound <= 4) dc = 2;
+        else if (bound <= 8) dc = 3;
+        else return -1;
+    }
+    *W_out = (int)W;
+    return (N - 1) * NDCLS + dc;
+}
+
+// Wave-aggregated "reserve one slot in counter[key]" -- returns the rank of
+// this lane among lanes of the wave with the same key plus the counter's old
+// value.  Lanes with key < 0 do nothing and get -1.
+__device__ int wave_reserve(int key, int *counter)
+{
+    const int lane = __lane_id();
+    bool pending = key >= 0;
+    int pos = -1;
+    for (;;) {
+        const unsigned long long act = __ballot(pending);
+        if (act == 0) break;
+        const int leader = __ffsll((long long)act) - 1;
+        const int k0 = __shfl(key, leader);
+        const bool mine = pending && key == k0;
+        const unsigned long long mask = __ballot(mine);
+        if (mine) {
+            const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&counter[k0], __popcll(mask));
+            base = __shfl(base, leader);
+            pos = base + rank;
+            pending = false;
+        }
+    }
+    return pos;
+}
+
+// hist[key] += candidates with that key; hist[NKEYS + key] = max W among them.
+__global__ void k_prep_count(const int *types, const int *len, const int *lo, const int *hi,
+                             int nmax, const int *sel, const int *nsel, int M, int num_types,
+                             int exact, int *keys, int *hist, int *status)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = __lane_id();
+    const int lim = nsel ? *nsel : M;
+    int key = -1, W = 0;
+    if (i < lim) {
+        const int m = sel ? sel[i] : i;
+        key = cand_key(types, len, lo, hi, nmax, m, num_types, exact, &W);
+        if (key < 0) atomicOr(status, ST_BADCAND);
+        keys[i] = key;
+    }
+    bool pending = key >= 0;
+    for (;;) {
+        const unsigned long long act = __ballot(pending);
+        if (act == 0) break;
+        const int leader = __ffsll((long long)act) - 1;
+        const int k0 = __shfl(key, leader);
+        const bool mine = pending && key == k0;
+        int wm = mine ? W : 0;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const int o = __shfl_xor(wm, off);
+            wm = o > wm ? o : wm;
+        }
+        const int cntk = __popcll(__ballot(mine));
+        if (lane == leader) {
+            atomicAdd(&hist[k0], cntk);
+            atomicMax(&hist[NKEYS + k0], wm);
+        }
+        pending = pending && !mine;
+    }
+}
+
+void launch_prep_count(const int *types, const int *len, const int *lo, const int *hi, int nmax,
+                       const int *sel, const int *nsel, int M, int num_types, int exact,
+                       int *keys, int *hist, int *status, hipStream_t s)
+{
+    if (M <= 0) return;
+    hipLaunchKernelGGL(k_prep_count, dim3((M + 255) / 256), dim3(256), 0, s, types, len, lo, hi,
+                       nmax, sel, nsel, M, num_types, exact, keys, hist, status);
+}
+
+__global__ void k_prep_scatter(const int *types, const int *len, const int *lo, const int *hi,
+                               int nmax, const int *sel, const int *nsel, int M,
+                               const int *keys, Layout lay, int *fill, int *pk, int *orig,
+                               int *tileW)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lim = nsel ? *nsel : M;
+    const int key = i < lim ? keys[i] : -1;
+    const int r = wave_reserve(key, fill);
+    if (key < 0) return;
+    const int m = sel ? sel[i] : i;
+    const int N = key / NDCLS + 1;
+    const int tile = lay.tile_base[key] + r / WAVE;
+    const int lane = r % WAVE;
+    int *rec = pk + lay.rec_base[key] + (int64_t)(r / WAVE) * rec_ints(N);
+    const int64_t tb = (int64_t)m * nmax, ib = (int64_t)m * (nmax - 1);
+    int W = 0;
+    for (int k = 0; k < N; ++k) rec[k * WAVE + lane] = types[tb + k];
+    for (int k = 0; k < N - 1; ++k) {
+        rec[(N + k) * WAVE + lane] = lo[ib + k];
+        rec[(2 * N - 1 + k) * WAVE + lane] = hi[ib + k];
+        W += hi[ib + k];
+    }
+    orig[(int64_t)tile * WAVE + lane] = m;
+    atomicMax(&tileW[tile], W);
+}
+
+void launch_prep_scatter(const int *types, const int *len, const int *lo, const int *hi,
+                         int nmax, const int *sel, const int *nsel, int M, const int *keys,
+                         const Layout &lay, int *fill, int *pk, int *orig, int *tileW,
+                         hipStream_t s)
+{
+    if (M <= 0) return;
+    hipLaunchKernelGGL(k_prep_scatter, dim3((M + 255) / 256), dim3(256), 0, s, types, len, lo,
+                       hi, nmax, sel, nsel, M, keys, lay, fill, pk, orig, tileW);
+}
+
+// ------------------------------------------------------------------ segment plan
+// lam[tile*(P+1)+p] = first index i with ticks[i] >= ticks[L_p] - W(tile),
+// L_p = p*n/P; lam[.., 0] = 0 and lam[.., P] = n.
+__global__ void k_plan(const int *__restrict__ ticks, int n, const int *__restrict__ tileW,
+                       int tiles, int P, int *__restrict__ lam)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)tiles * (P + 1)) return;
+    const int tile = (int)(i / (P + 1)), p = (int)(i % (P + 1));
+    if (p == 0) { lam[i] = 0; return; }
+    if (p == P) { lam[i] = n; return; }
+    const int L = (int)((int64_t)p * n / P);
+    const int x = ticks[L] - tileW[tile];
+    int a = 0, b = L;
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (ticks[mid] < x) a = mid + 1;
+        else b = mid;
+    }
+    lam[i] = a;
+}
+
+void launch_plan(const int *ticks, int n, const int *tileW, int tiles, int P, int *lam,
+                 hipStream_t s)
+{
+    const int64_t tot = (int64_t)tiles * (P + 1);
+    hipLaunchKernelGGL(k_plan, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, ticks, n,
+                       tileW, tiles, P, lam);
+}
+
+// ------------------------------------------------------------------ Map dispatch
+void launch_map_n1(bool, int, const MapGroup &, hipStream_t, bool);
+void launch_map_n2(bool, int, const MapGroup &, hipStream_t, bool);
+void launch_map_n3(bool, int, const MapGroup &, hipStream_t, bool);
+void launch_map_n4(bool, int, const MapGroup &, hipStream_t, bool);
+void launch_map_n5(bool, int, const MapGroup &, hipStream_t, bool);
+void launch_map_n6(bool, int, const MapGroup &, hipStream_t, bool);
+void launch_map_n7(bool, int, const MapGroup &, hipStream_t, bool);
+void launch_map_n8(bool, int, const MapGroup &, hipStream_t, bool);
+
+static void dispatch(int N, bool exact, int dcls, const MapGroup &g, hipStream_t s, bool fix)
+{
+    switch (N) {
+    case 1: return launch_map_n1(exact, dcls, g, s, fix);
+    case 2: return launch_map_n2(exact, dcls, g, s, fix);
+    case 3: return launch_map_n3(exact, dcls, g, s, fix);
+    case 4: return launch_map_n4(exact, dcls, g, s, fix);
+    case 5: return launch_map_n5(exact, dcls, g, s, fix);
+    case 6: return launch_map_n6(exact, dcls, g, s, fix);
+    case 7: return launch_map_n7(exact, dcls, g, s, fix);
+    default: return launch_map_n8(exact, dcls, g, s, fix);
+    }
+}
+
+void launch_map(int N, bool exact, int dcls, const MapGroup &g, hipStream_t s)
+{
+    dispatch(N, exact, dcls, g, s, false);
+}
+
+void launch_fixup(int N, bool exact, int dcls, const MapGroup &g, hipStream_t s)
+{
+    dispatch(N, exact, dcls, g, s, true);
+}
+
+// ------------------------------------------------------------------ Concatenate
+// (c, x) o (c', x')[sigma] = (c[sigma] + c'[x[sigma]], x'[x[sigma]]); the
+// count is the composition over all segments applied to slot 0 of segment 0.
+__device__ __forceinline__ int clampk(int x) { return x < 0 ? 0 : (x >= KMAX ? KMAX - 1 : x); }
+
+__global__ void k_concat_seq(MapGroup g)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.tiles * WAVE) return;
+    const int o = g.orig[c];
+    if (o < 0 || g.flags[c]) return;
+    const int64_t stride = (int64_t)g.tiles * WAVE * KMAX;
+    const int2 *t = g.tbl + (int64_t)c * KMAX;
+    int x = 0, tot = 0;
+    for (int p = 0; p < g.P; ++p) {
+        const int2 v = t[p * stride + x];
+        tot += v.x;
+        x = clampk(v.y);
+    }
+    g.out[o] = tot;
+}
+
+// One wave per candidate: lane l composes a contiguous chunk of segments
+// sequentially, then the 64 chunk tables are composed by a shuffle tree.
+__global__ __launch_bounds__(WAVE *WPB) void k_concat_tree(MapGroup g)
+{
+    const int lane = __lane_id();
+    const int c = uniform_u(blockIdx.x * WPB + (threadIdx.x >> 6));
+    if (c >= g.tiles * WAVE) return;
+    const int o = g.orig[c];
+    if (o < 0 || g.flags[c]) return;
+    const int P = g.P;
+    const int cs = (P + WAVE - 1) / WAVE;
+    const int p0 = lane * cs;
+    const int p1 = p0 + cs < P ? p0 + cs : P;
+    const int64_t stride = (int64_t)g.tiles * WAVE * KMAX;
+    const int2 *t = g.tbl + (int64_t)c * KMAX;
+    int tc[KMAX], tx[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+        int x = j, tot = 0;
+        for (int p = p0; p < p1; ++p) {
+            const int2 v = t[p * stride + x];
+            tot += v.x;
+            x = clampk(v.y);
+        }
+        tc[j] = tot;
+        tx[j] = x;
+    }
+#pragma unroll
+    for (int s = 1; s < WAVE; s <<= 1) {
+        int pc[KMAX], px[KMAX];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) {
+            pc[j] = __shfl(tc[j], lane + s < WAVE ? lane + s : lane);
+            px[j] = __shfl(tx[j], lane + s < WAVE ? lane + s : lane);
+        }
+        if ((lane & (2 * s - 1)) == 0 && lane + s < WAVE) {
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j) {
+                int ac = 0, ax = 0;
+#pragma unroll
+                for (int q = 0; q < KMAX; ++q)
+                    if (tx[j] == q) { ac = pc[q]; ax = px[q]; }
+                tc[j] += ac;
+                tx[j] = ax;
+            }
+        }
+    }
+    if (lane == 0) g.out[o] = tc[0];
+}
+
+void launch_concat(const MapGroup &g, bool tree, hipStream_t s)
+{
+    const int cands = g.tiles * WAVE;
+    if (tree)
+        hipLaunchKernelGGL(k_concat_tree, dim3((cands + WPB - 1) / WPB), dim3(WAVE * WPB), 0, s, g);
+    else
+        hipLaunchKernelGGL(k_concat_seq, dim3((cands + 255) / 256), dim3(256), 0, s, g);
+}
+
+// ------------------------------------------------------------------ elimination
+// Algorithm 4's elimination: keep m when vals[m] >= theta (appending m to
+// sel), else write -1 into pruned_out[m].
+__global__ void k_compact(const int *vals, int M, int theta, int *pruned_out, int *sel, int *nsel)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = i < M;
+    const bool keep = in && vals[i] >= theta;
+    if (in && !keep && pruned_out) pruned_out[i] = -1;
+    const int r = wave_reserve(keep ? 0 : -1, nsel);
+    if (keep) sel[r] = i;
+}
+
+void launch_compact(const int *vals, int M, int theta, int *pruned_out, int *sel, int *nsel,
+                    hipStream_t s)
+{
+    if (M <= 0) return;
+    hipLaunchKernelGGL(k_compact, dim3((M + 255) / 256), dim3(256), 0, s, vals, M, theta,
+                       pruned_out, sel, nsel);
+}
+
+// out_a[i] = a[sel[i]], out_b[i] = b[sel[i]] for i < *nsel
+__global__ void k_gather2(const int *a, const int *b, const int *sel, const int *nsel, int *out_a,
+                          int *out_b)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= *nsel) return;
+    out_a[i] = a[sel[i]];
+    out_b[i] = b[sel[i]];
+}
+
+void launch_gather2(const int *a, const int *b, const int *sel, const int *nsel, int M, int *out_a,
+                    int *out_b, hipStream_t s)
+{
+    if (M <= 0) return;
+    hipLaunchKernelGGL(k_gather2, dim3((M + 255) / 256), dim3(256), 0, s, a, b, sel, nsel, out_a,
+                       out_b);
+}
+
+// ------------------------------------------------------------------ level 1
+__global__ void k_histogram(const int *__restrict__ ids, int n, int num_types, int *hist)
+{
+    extern __shared__ int sh[];
+    const bool lds = num_types <= 8192;
+    if (lds)
+        for (int k = threadIdx.x; k < num_types; k += blockDim.x) sh[k] = 0;
+    __syncthreads();
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int e = ids[i];
+        if (e < 0 || e >= num_types) continue;
+        if (lds) atomicAdd(&sh[e], 1);
+        else atomicAdd(&hist[e], 1);
+    }
+    __syncthreads();
+    if (lds)
+        for (int k = threadIdx.x; k < num_types; k += blockDim.x)
+            if (sh[k]) atomicAdd(&hist[k], sh[k]);
+}
+
+void launch_histogram(const int *ids, int n, int num_types, int *hist, hipStream_t s)
+{
+    if (n <= 0) return;
+    int blocks = (n + 4095) / 4096;
+    if (blocks > 1024) blocks = 1024;
+    const size_t sh = num_types <= 8192 ? (size_t)num_types * sizeof(int) : 0;
+    hipLaunchKernelGGL(k_histogram, dim3(blocks), dim3(256), sh, s, ids, n, num_types, hist);
+}
+
+}  // namespace fe

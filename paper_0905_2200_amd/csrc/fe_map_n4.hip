@@ -1,0 +1,9 @@
+// Map / fixup kernels for 4-node episodes (all counter variants).
+#include "fe_map.h"
+
+namespace fe {
+void launch_map_n4(bool exact, int dcls, const MapGroup &g, hipStream_t s, bool fix)
+{
+    map_dispatch_n<4>(exact, dcls, g, s, fix);
+}
+}  // namespace fe
