@@ -1,8 +1,8 @@
 """Thin ctypes binding of libfe.so (the C ABI in include/fe.h).
 
 Argument marshalling only: tensors go in as device pointers, work is
-enqueued on the current torch stream of the device, every step runs in the
-library's HIP kernels.  There is no fallback: if the library or a GPU is
+enqueued on the context's stream (fenced against the caller's current torch
+stream), every step runs in the library's HIP kernels.  There is no fallback: if the library or a GPU is
 missing, :func:`lib` raises.
 """
 from __future__ import annotations
@@ -102,14 +102,20 @@ def _dev_i32(x, device):
 
 
 class Context:
-    """A library context bound to one device and the current torch stream."""
+    """A library context bound to one device and one torch stream.
+
+    By default the context owns a torch stream of its own (default
+    priority).  Every call first makes that stream wait for the caller's
+    current stream and afterwards makes the current stream wait for it, so
+    tensors produced or consumed around a call are ordered like any torch
+    op on the current stream."""
 
     def __init__(self, device=0, stream=None):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         if stream is None:
-            stream = torch.cuda.current_stream(self.device)
+            stream = torch.cuda.Stream(self.device)
         self.stream = stream
         h = ctypes.c_void_p()
         rc = lib().fe_create(self.device.index or 0, ctypes.c_void_p(stream.cuda_stream),
@@ -136,6 +142,23 @@ class Context:
         self.close()
 
     # ------------------------------------------------------------------ helpers
+    def _enter(self):
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+
+    def _leave(self):
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            cur.wait_stream(self.stream)
+
+    def _call(self, fn, *args):
+        self._enter()
+        try:
+            return fn(*args)
+        finally:
+            self._leave()
+
     def _check(self, rc):
         if rc != FE_OK:
             raise FeError(rc, lib().fe_last_error(self.h).decode())
@@ -154,7 +177,7 @@ class Context:
         return {k: getattr(s, k) for k, _ in _Stats._fields_}
 
     def sync(self):
-        self._check(lib().fe_sync(self.h))
+        self._check(self._call(lib().fe_sync, self.h))
 
     def stream_tensors(self, ids, ticks):
         return _dev_i32(ids, self.device), _dev_i32(ticks, self.device)
@@ -175,14 +198,15 @@ class Context:
 
     # ------------------------------------------------------------------ API
     def validate(self, ids, ticks, num_types):
-        self._check(lib().fe_validate(self.h, _ptr(ids), _ptr(ticks), ids.numel(), int(num_types)))
+        self._check(self._call(lib().fe_validate, self.h, _ptr(ids), _ptr(ticks), ids.numel(),
+                               int(num_types)))
 
     def count(self, ids, ticks, num_types, cand, mode=FE_EXACT, out=None):
         c = cand if "nmax" in cand and hasattr(cand["types"], "data_ptr") else self.cand_tensors(cand)
         M = c["M"]
         if out is None:
             out = self.torch.empty(max(M, 1), dtype=self.torch.int32, device=self.device)
-        rc = lib().fe_count(self.h, _ptr(ids), _ptr(ticks), ids.numel(), int(num_types),
+        rc = self._call(lib().fe_count, self.h, _ptr(ids), _ptr(ticks), ids.numel(), int(num_types),
                             _ptr(c["types"]), _ptr(c["len"]), _ptr(c["lo"]), _ptr(c["hi"]),
                             M, c["nmax"], int(mode), _ptr(out))
         self._check(rc)
@@ -199,7 +223,7 @@ class Context:
             exact = t.empty(max(M, 1), dtype=t.int32, device=self.device)
         if nsurv is None:
             nsurv = t.zeros(1, dtype=t.int32, device=self.device)
-        rc = lib().fe_count_two_pass(self.h, _ptr(ids), _ptr(ticks), ids.numel(), int(num_types),
+        rc = self._call(lib().fe_count_two_pass, self.h, _ptr(ids), _ptr(ticks), ids.numel(), int(num_types),
                                      _ptr(c["types"]), _ptr(c["len"]), _ptr(c["lo"]), _ptr(c["hi"]),
                                      M, c["nmax"], int(theta), _ptr(upper), _ptr(exact),
                                      _ptr(nsurv))
@@ -213,7 +237,7 @@ class Context:
         ilo = np.ascontiguousarray(np.asarray([a for a, _ in intervals], np.int32))
         ihi = np.ascontiguousarray(np.asarray([b for _, b in intervals], np.int32))
         res = ctypes.POINTER(_Result)()
-        rc = lib().fe_mine(self.h, _ptr(ids), _ptr(ticks), ids.numel(), int(num_types),
+        rc = self._call(lib().fe_mine, self.h, _ptr(ids), _ptr(ticks), ids.numel(), int(num_types),
                            ilo.ctypes.data_as(ctypes.c_void_p), ihi.ctypes.data_as(ctypes.c_void_p),
                            len(intervals), int(theta), int(max_level), ctypes.byref(res))
         self._check(rc)
