@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the episode-counting hot path on one MI355X.
+
+One step = one full level-wise mining run (Problem 1) on the mining
+workload: 64 neurons firing at 20 Hz for 780 s (about 1.05M events, int32
+ids and 0.1 ms int32 ticks) with eight planted cascades of 3-6 nodes, hop
+intervals {(0,5], (5,10], (10,20]} ms, levels 2-6, threshold 0.5 Hz x 780 s
+= 390.  Every level is generated on the host and counted on the GPU with
+two-pass elimination (relaxed pass, elimination, exact pass on survivors),
+each pass by MapConcatenate Map/Concatenate kernels.
+
+Metric: candidate-episode x events per second, where a step's work is
+sum over levels >= 2 of (candidates + survivors) x n events.  The stream
+is resident in HBM before timing starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_EE = 8  # one int32 id + one int32 tick per event per candidate machine
+MAP_SOURCES = ["paper_0905_2200_amd/csrc/fe_map.h"] + [
+    "paper_0905_2200_amd/csrc/fe_map_n%d.hip" % n for n in range(1, 9)]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def map_source_hash():
+    h = hashlib.sha256()
+    for p in MAP_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current Map sources (else None)."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("map_source_hash") != map_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(stream, target_s, n_types, intervals, theta):
+    """The oracle's two-pass counter (projection mode, all host threads) on
+    a seeded uniform sample of the level-3 candidate set of the same
+    workload (random 3-node episodes over the 64 types and the interval
+    set), grown until about target_s seconds of CPU work."""
+    import numpy as np
+    import oracle
+    from paper_0905_2200_amd import synth
+    ids, ticks = stream["ids"], stream["ticks"]
+    rng = np.random.default_rng([2, 777])
+    total_ee, total_s, M_done = 0.0, 0.0, 0
+    chunk = 2000
+    threads = oracle.max_threads()
+    while total_s < target_s and M_done < 2_000_000:
+        eps = synth.random_episodes(rng, chunk, n_types, 3, intervals)
+        c = synth.pack(eps)
+        t0 = time.perf_counter()
+        up, ex = oracle.two_pass(ids, ticks, n_types, c["types"], c["len"], c["lo"], c["hi"],
+                                 theta, projection=True, nthreads=threads)
+        dt = time.perf_counter() - t0
+        total_s += dt
+        total_ee += float(chunk + int((up >= theta).sum())) * ids.size
+        M_done += chunk
+        if dt < target_s / 8:
+            chunk *= 2
+    return {"value": total_ee / total_s, "unit": "ee/s", "cores": threads, "kind": "oracle",
+            "sample": ("two-pass (relaxed pass, elimination, exact pass) in projection mode on "
+                       "%d random level-3 episodes of the mining workload over its %d events, "
+                       "%.1f s" % (M_done, ids.size, total_s))}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--duration-s", type=float, default=780.0,
+                    help="stream duration of the mining workload (default 780 s)")
+    ap.add_argument("--max-level", type=int, default=6)
+    ap.add_argument("--cpu-baseline-s", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        if int(os.environ.get("RANK", "0")) == 0:
+            print("bench.py measures one GPU: the counting path runs on a single device here; "
+                  "--gpus %d is not supported" % max(args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_0905_2200_amd import fe, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    fe.lib()  # fails loudly when the HIP library is not built
+
+    s = synth.config_mining(duration_s=args.duration_s)
+    n = int(s["ids"].size)
+    theta, intervals = s["theta"], s["intervals"]
+    log("workload: %s; n=%d theta=%d" % (s["name"], n, theta))
+
+    ctx = fe.Context(0)
+    ids, ticks = ctx.stream_tensors(s["ids"], s["ticks"])
+    torch.cuda.synchronize()
+
+    if args.calib_copy_mib:
+        a = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def step():
+        return ctx.mine(ids, ticks, s["num_types"], intervals, theta, args.max_level)
+
+    for w in range(args.warmup):
+        t0 = time.perf_counter()
+        res = step()
+        torch.cuda.synchronize()
+        log("warmup step %d: %.2f s" % (w, time.perf_counter() - t0))
+
+    ctx.set_param(fe.PARAM_TIMING, 1)
+    ctx.reset_kernel_stats()
+    times = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        res = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log("step %d: %.3f s" % (len(times) - 1, times[-1]))
+    t_total = time.perf_counter() - t_start
+    kst = ctx.kernel_stats()
+    ctx.set_param(fe.PARAM_TIMING, 0)
+
+    ee_step = sum((lv["n_candidates"] + lv["n_survivors"]) * n for lv in res if lv["level"] >= 2)
+    value = ee_step * args.steps / t_total
+    for lv in res:
+        log("level %d: candidates %d survivors %d frequent %d gen %.1f ms count %.1f ms" % (
+            lv["level"], lv["n_candidates"], lv["n_survivors"], lv["n_frequent"],
+            lv["gen_ms"], lv["count_ms"]))
+    tot_kms = sum(v["total_ms"] for v in kst.values())
+    for k, v in sorted(kst.items(), key=lambda kv: -kv[1]["total_ms"]):
+        log("kernel %-24s launches %5d total %9.2f ms (%.1f%%) ee %.3e" % (
+            k, v["launches"], v["total_ms"], 100 * v["total_ms"] / max(tot_kms, 1e-9), v["ee"]))
+
+    maps = {k: v for k, v in kst.items() if k.startswith("map_") and v["total_ms"] > 0}
+    dom = max(maps.items(), key=lambda kv: kv[1]["total_ms"]) if maps else None
+    roofline = None
+    if dom:
+        name, v = dom
+        achieved = BYTES_PER_EE * v["ee"] / (v["total_ms"] * 1e-3) / 1e9
+        tb = traffic_for(name)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": tb, "kernel": name,
+                    "avg_launch_ms": round(v["total_ms"] / v["launches"], 4),
+                    "launches": v["launches"],
+                    "ee_per_s": v["ee"] / (v["total_ms"] * 1e-3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(s, args.cpu_baseline_s, s["num_types"], intervals, theta)
+        cpu["value"] = float("%.4g" % cpu["value"])
+
+    times_ms = sorted(1e3 * t for t in times)
+    out = {
+        "metric": "candidate-episode×events/s",
+        "value": float("%.5g" % value),
+        "unit": "ee/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_total / args.steps, 2),
+        "p50_ms": round(float(np.percentile(times_ms, 50)), 2),
+        "p99_ms": round(float(np.percentile(times_ms, 99)), 2),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "level-wise mining, two-pass, levels 2-%d" % args.max_level,
+                   "neurons": s["num_types"], "rate_hz": 20, "duration_s": args.duration_s,
+                   "n_events": n, "theta": theta, "intervals_ticks": intervals,
+                   "ee_per_step": ee_step,
+                   "levels": [{k: lv[k] for k in ("level", "n_candidates", "n_survivors",
+                                                   "n_frequent")} for lv in res]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

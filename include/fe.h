@@ -82,8 +82,10 @@ typedef enum fe_param {
     FE_PARAM_SEGMENTS = 0,   /* MapConcatenate segment count P; 0 = automatic  */
     FE_PARAM_TARGET_WAVES = 1, /* waves the automatic P aims for per launch    */
     FE_PARAM_MIN_SEG_EVENTS = 2, /* smallest segment the automatic P allows   */
-    FE_PARAM_CONCAT_TREE = 3 /* 1 = wave-shuffle tree Concatenate when P >= 16,
-                                0 = per-candidate sequential walk              */
+    FE_PARAM_CONCAT_TREE = 3, /* 1 = wave-shuffle tree Concatenate when P >= 16,
+                                 0 = per-candidate sequential walk             */
+    FE_PARAM_TIMING = 4      /* 1 = time every kernel launch with HIP events on
+                                the context's stream (fe_get_kernel_stats)     */
 } fe_param;
 
 typedef struct fe_ctx fe_ctx;
@@ -182,6 +184,24 @@ typedef struct fe_stats {
 } fe_stats;
 
 int fe_get_stats(const fe_ctx *ctx, fe_stats *out);
+
+/* Per-kernel timing (FE_PARAM_TIMING = 1): for each kernel kind, the number
+ * of launches, their summed and largest duration measured with HIP events
+ * recorded around each launch on the context's stream, and the algorithmic
+ * work they did in candidate-episode x event units (candidates counted x
+ * stream events; 0 for kernels that do not scan the stream). */
+typedef struct fe_kernel_stat {
+    char name[40];
+    int64_t launches;
+    double total_ms;
+    double max_ms;
+    double ee;
+} fe_kernel_stat;
+
+/* Copies up to cap entries into out, sets *n_out to the number of kinds.
+ * Synchronises the context's stream. */
+int fe_get_kernel_stats(fe_ctx *ctx, fe_kernel_stat *out, int32_t cap, int32_t *n_out);
+int fe_reset_kernel_stats(fe_ctx *ctx);
 
 #ifdef __cplusplus
 }

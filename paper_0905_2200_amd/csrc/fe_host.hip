@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -38,13 +39,26 @@ struct fe_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
-    int64_t param[4] = {0, 4096, 1024, 1};
+    int64_t param[5] = {0, 4096, 1024, 1, 0};
     fe_stats stats{};
     // workspace
     Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small;
     Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn;
     int *host = nullptr;  // pinned host staging for small readbacks
     size_t host_cap = 0;
+    // kernel timing
+    struct Pending {
+        std::string name;
+        double ee;
+        hipEvent_t a, b;
+    };
+    struct Agg {
+        int64_t launches = 0;
+        double total_ms = 0, max_ms = 0, ee = 0;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    std::map<std::string, Agg> kstats;
 };
 
 namespace {
@@ -114,6 +128,68 @@ int ensure_host(fe_ctx *c, size_t ints)
 
 template <class T> T *P(Buf &b) { return (T *)b.p; }
 
+// ---- kernel timing with HIP events on the context's stream
+hipEvent_t pool_event(fe_ctx *c)
+{
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+int resolve_timers(fe_ctx *c)
+{
+    if (c->pending.empty()) return FE_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) {
+            (void)hipGetLastError();
+            ms = 0.f;
+        }
+        auto &g = c->kstats[p.name];
+        g.launches++;
+        g.total_ms += ms;
+        g.max_ms = std::max(g.max_ms, (double)ms);
+        g.ee += p.ee;
+        c->event_pool.push_back(p.a);
+        c->event_pool.push_back(p.b);
+    }
+    c->pending.clear();
+    return FE_OK;
+}
+
+// Scoped timer: records an event before and after the launches in its scope.
+struct KTimer {
+    fe_ctx *c;
+    bool on;
+    fe_ctx::Pending p;
+    KTimer(fe_ctx *c_, const char *name, double ee) : c(c_), on(c_->param[FE_PARAM_TIMING] != 0)
+    {
+        if (!on) return;
+        p.name = name;
+        p.ee = ee;
+        p.a = pool_event(c);
+        p.b = pool_event(c);
+        if (!p.a || !p.b) { on = false; return; }
+        (void)hipEventRecord(p.a, c->stream);
+    }
+    ~KTimer()
+    {
+        if (!on) return;
+        (void)hipEventRecord(p.b, c->stream);
+        c->pending.push_back(p);
+        if (c->pending.size() > 4096) (void)resolve_timers(c);
+    }
+};
+
 int status_code(int bits)
 {
     if (bits & ST_BADCAND) return FE_EINVAL;
@@ -175,8 +251,11 @@ int run_pass(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, 
     int *hist = P<int>(c->hist);
     launch_fill(hist, 0, 2 * NKEYS, s);
     launch_fill(P<int>(c->fill), 0, NKEYS, s);
-    launch_prep_count(cin.types, cin.len, cin.lo, cin.hi, cin.nmax, sel, nsel, M, num_types,
-                      exact ? 1 : 0, P<int>(c->keys), hist, P<int>(c->status), s);
+    {
+        KTimer kt(c, "prep_count", 0);
+        launch_prep_count(cin.types, cin.len, cin.lo, cin.hi, cin.nmax, sel, nsel, M, num_types,
+                          exact ? 1 : 0, P<int>(c->keys), hist, P<int>(c->status), s);
+    }
     if ((rc = ensure_host(c, 2 * NKEYS + 1))) return rc;
     HIPCHK(c, hipMemcpyAsync(c->host, hist, NKEYS * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(c->host + NKEYS + 1, hist + NKEYS, NKEYS * sizeof(int),
@@ -211,12 +290,15 @@ int run_pass(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, 
     if ((rc = ensure(c, c->pk, (size_t)rec_total * sizeof(int)))) return rc;
     if ((rc = ensure(c, c->orig, (size_t)tiles_total * WAVE * sizeof(int)))) return rc;
     if ((rc = ensure(c, c->tileW, (size_t)tiles_total * sizeof(int)))) return rc;
-    launch_fill(P<int>(c->pk), -1, rec_total, s);
-    launch_fill(P<int>(c->orig), -1, (int64_t)tiles_total * WAVE, s);
-    launch_fill(P<int>(c->tileW), 0, tiles_total, s);
-    launch_prep_scatter(cin.types, cin.len, cin.lo, cin.hi, cin.nmax, sel, nsel, M,
-                        P<int>(c->keys), lay, P<int>(c->fill), P<int>(c->pk), P<int>(c->orig),
-                        P<int>(c->tileW), s);
+    {
+        KTimer kt(c, "prep_scatter", 0);
+        launch_fill(P<int>(c->pk), -1, rec_total, s);
+        launch_fill(P<int>(c->orig), -1, (int64_t)tiles_total * WAVE, s);
+        launch_fill(P<int>(c->tileW), 0, tiles_total, s);
+        launch_prep_scatter(cin.types, cin.len, cin.lo, cin.hi, cin.nmax, sel, nsel, M,
+                            P<int>(c->keys), lay, P<int>(c->fill), P<int>(c->pk),
+                            P<int>(c->orig), P<int>(c->tileW), s);
+    }
 
     for (int k = 0; k < NKEYS; ++k) {
         if (!cnt[k]) continue;
@@ -236,6 +318,10 @@ int run_pass(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, 
         g.flags = nullptr;
         g.P = choose_P(c, tiles, si, wmax[k]);
         c->stats.map_launches++;
+        char kname[40];
+        snprintf(kname, sizeof kname, "map_%s_n%d_d%d", exact ? "exact" : "relaxed", N,
+                 exact ? dcls_depth(dcls) : 1);
+        const double ee = (double)cnt[k] * (double)si.n;
         c->stats.segments_max = std::max<int64_t>(c->stats.segments_max, g.P);
         if (g.P > 1) {
             const int64_t lam_n = (int64_t)tiles * (g.P + 1);
@@ -246,12 +332,27 @@ int run_pass(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, 
             g.lam = P<int>(c->lam);
             g.tbl = P<int2>(c->tbl);
             g.flags = P<int>(c->flags);
-            launch_fill(g.flags, 0, (int64_t)tiles * WAVE, s);
-            launch_plan(ticks, si.n, P<int>(c->tileW) + lay.tile_base[k], tiles, g.P, P<int>(c->lam), s);
-            launch_map(N, exact, dcls, g, s);
-            launch_concat(g, c->param[FE_PARAM_CONCAT_TREE] && g.P >= 16, s);
-            launch_fixup(N, exact, dcls, g, s);
+            {
+                KTimer kt(c, "plan", 0);
+                launch_fill(g.flags, 0, (int64_t)tiles * WAVE, s);
+                launch_plan(ticks, si.n, P<int>(c->tileW) + lay.tile_base[k], tiles, g.P,
+                            P<int>(c->lam), s);
+            }
+            {
+                KTimer kt(c, kname, ee);
+                launch_map(N, exact, dcls, g, s);
+            }
+            {
+                const bool tree = c->param[FE_PARAM_CONCAT_TREE] && g.P >= 16;
+                KTimer kt(c, tree ? "concat_tree" : "concat_seq", 0);
+                launch_concat(g, tree, s);
+            }
+            {
+                KTimer kt(c, "fixup", 0);
+                launch_fixup(N, exact, dcls, g, s);
+            }
         } else {
+            KTimer kt(c, kname, ee);
             launch_map(N, exact, dcls, g, s);
         }
         HIPCHK(c, hipGetLastError());
@@ -335,7 +436,10 @@ int two_pass_impl(fe_ctx *c, const int32_t *ids, const int32_t *ticks, const Str
     if ((rc = ensure(c, c->sel, (size_t)M * sizeof(int)))) return rc;
     // empty stream: every count is 0, so kept candidates keep exact = 0
     if (si.n == 0) launch_fill(exact, 0, M, s);
-    launch_compact(upper, M, theta, exact, P<int>(c->sel), P<int>(c->nsel), s);
+    {
+        KTimer kt(c, "compact", 0);
+        launch_compact(upper, M, theta, exact, P<int>(c->sel), P<int>(c->nsel), s);
+    }
     if (si.n > 0 &&
         (rc = run_pass(c, ids, ticks, si, num_types, cin, P<int>(c->sel), P<int>(c->nsel), M,
                        true, exact)))
@@ -384,6 +488,11 @@ extern "C" int fe_destroy(fe_ctx *c)
                    &c->mtypes, &c->mlen, &c->mlo, &c->mhi, &c->mup, &c->mex, &c->msel, &c->mn};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
+    for (auto &p : c->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     if (c->host) (void)hipHostFree(c->host);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -415,7 +524,7 @@ extern "C" int fe_sync(fe_ctx *c)
 extern "C" int fe_set_param(fe_ctx *c, int param, int64_t value)
 {
     if (!c) return FE_EINVAL;
-    if (param < 0 || param > 3 || value < 0) return fail(c, FE_EINVAL, "bad parameter");
+    if (param < 0 || param > 4 || value < 0) return fail(c, FE_EINVAL, "bad parameter");
     if (param == FE_PARAM_TARGET_WAVES && value == 0) return fail(c, FE_EINVAL, "bad parameter");
     c->param[param] = value;
     return FE_OK;
@@ -423,7 +532,7 @@ extern "C" int fe_set_param(fe_ctx *c, int param, int64_t value)
 
 extern "C" int fe_get_param(const fe_ctx *c, int param, int64_t *value)
 {
-    if (!c || !value || param < 0 || param > 3) return FE_EINVAL;
+    if (!c || !value || param < 0 || param > 4) return FE_EINVAL;
     *value = c->param[param];
     return FE_OK;
 }
@@ -432,6 +541,39 @@ extern "C" int fe_get_stats(const fe_ctx *c, fe_stats *out)
 {
     if (!c || !out) return FE_EINVAL;
     *out = c->stats;
+    return FE_OK;
+}
+
+extern "C" int fe_get_kernel_stats(fe_ctx *c, fe_kernel_stat *out, int32_t cap, int32_t *n_out)
+{
+    if (!c || !n_out || cap < 0 || (cap > 0 && !out)) return FE_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc;
+    if ((rc = resolve_timers(c))) return rc;
+    int i = 0;
+    for (auto &kv : c->kstats) {
+        if (i < cap) {
+            fe_kernel_stat &o = out[i];
+            std::memset(&o, 0, sizeof o);
+            std::snprintf(o.name, sizeof o.name, "%s", kv.first.c_str());
+            o.launches = kv.second.launches;
+            o.total_ms = kv.second.total_ms;
+            o.max_ms = kv.second.max_ms;
+            o.ee = kv.second.ee;
+        }
+        ++i;
+    }
+    *n_out = i;
+    return FE_OK;
+}
+
+extern "C" int fe_reset_kernel_stats(fe_ctx *c)
+{
+    if (!c) return FE_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc;
+    if ((rc = resolve_timers(c))) return rc;
+    c->kstats.clear();
     return FE_OK;
 }
 

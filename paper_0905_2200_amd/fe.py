@@ -17,14 +17,14 @@ LIB_PATH = os.path.join(HERE, "libfe.so")
 
 FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_EUNSORTED, FE_ERANGE, FE_EBUSY, FE_EINTERNAL = range(8)
 FE_EXACT, FE_RELAXED = 0, 1
-PARAM_SEGMENTS, PARAM_TARGET_WAVES, PARAM_MIN_SEG_EVENTS, PARAM_CONCAT_TREE = range(4)
+PARAM_SEGMENTS, PARAM_TARGET_WAVES, PARAM_MIN_SEG_EVENTS, PARAM_CONCAT_TREE, PARAM_TIMING = range(5)
 
 STATUS_NAMES = {0: "FE_OK", 1: "FE_EINVAL", 2: "FE_ENOMEM", 3: "FE_EDEVICE",
                 4: "FE_EUNSORTED", 5: "FE_ERANGE", 6: "FE_EBUSY", 7: "FE_EINTERNAL"}
 
 EXPORTS = ["fe_create", "fe_destroy", "fe_last_error", "fe_sync", "fe_set_param",
            "fe_get_param", "fe_validate", "fe_count", "fe_count_two_pass", "fe_mine",
-           "fe_result_free", "fe_get_stats"]
+           "fe_result_free", "fe_get_stats", "fe_get_kernel_stats", "fe_reset_kernel_stats"]
 
 
 class FeError(RuntimeError):
@@ -49,6 +49,11 @@ class _Result(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("map_launches", ctypes.c_int64), ("segments_max", ctypes.c_int64),
                 ("fallback_cands", ctypes.c_int64), ("last_call_ms", ctypes.c_double)]
+
+
+class _KStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("ee", ctypes.c_double)]
 
 
 _lib = None
@@ -79,6 +84,9 @@ def lib():
                     ctypes.c_int),
         "fe_result_free": ([ctypes.POINTER(_Result)], None),
         "fe_get_stats": ([CTX, ctypes.POINTER(_Stats)], ctypes.c_int),
+        "fe_get_kernel_stats": ([CTX, ctypes.POINTER(_KStat), I32, ctypes.POINTER(I32)],
+                                ctypes.c_int),
+        "fe_reset_kernel_stats": ([CTX], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -175,6 +183,19 @@ class Context:
         s = _Stats()
         self._check(lib().fe_get_stats(self.h, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in _Stats._fields_}
+
+    def kernel_stats(self):
+        """{kernel kind: {launches, total_ms, max_ms, ee}} from the HIP-event
+        timers (enable with set_param(PARAM_TIMING, 1))."""
+        n = ctypes.c_int32()
+        self._check(self._call(lib().fe_get_kernel_stats, self.h, None, 0, ctypes.byref(n)))
+        arr = (_KStat * max(n.value, 1))()
+        self._check(self._call(lib().fe_get_kernel_stats, self.h, arr, n.value, ctypes.byref(n)))
+        return {a.name.decode(): {"launches": a.launches, "total_ms": a.total_ms,
+                                  "max_ms": a.max_ms, "ee": a.ee} for a in arr[:n.value]}
+
+    def reset_kernel_stats(self):
+        self._check(self._call(lib().fe_reset_kernel_stats, self.h))
 
     def sync(self):
         self._check(self._call(lib().fe_sync, self.h))
