@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace fe;
@@ -238,6 +239,84 @@ int choose_P(const fe_ctx *c, int tiles, const StreamInfo &si, int Wmax)
     return (int)std::max<int64_t>(P, 1);
 }
 
+// One candidate group (episode size and list-depth class) already packed
+// in the tile table: tiles [tile_base, tile_base+tiles), records from int
+// offset rec_base, widest W (sum of hi) wmax, real candidates ncand.
+struct GroupDesc {
+    int key;
+    int tiles;
+    int tile_base;
+    int64_t rec_base;
+    int wmax;
+    int64_t ncand;
+};
+
+// Map (+ plan, Concatenate, fix-up when segmented) for every packed group.
+int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si,
+                  const std::vector<GroupDesc> &groups, bool exact, int *out)
+{
+    hipStream_t s = c->stream;
+    int rc;
+    for (const GroupDesc &gd : groups) {
+        const int k = gd.key;
+        const int N = k / NDCLS + 1, dcls = k % NDCLS;
+        const int tiles = gd.tiles;
+        MapGroup g;
+        g.ids = ids;
+        g.ticks = ticks;
+        g.n = si.n;
+        g.pk = P<int>(c->pk) + gd.rec_base;
+        g.orig = P<int>(c->orig) + (int64_t)gd.tile_base * WAVE;
+        g.out = out;
+        g.status = P<int>(c->status);
+        g.tiles = tiles;
+        g.lam = nullptr;
+        g.tbl = nullptr;
+        g.flags = nullptr;
+        g.P = choose_P(c, tiles, si, gd.wmax);
+        c->stats.map_launches++;
+        char kname[40];
+        snprintf(kname, sizeof kname, "map_%s_n%d_d%d", exact ? "exact" : "relaxed", N,
+                 exact ? dcls_depth(dcls) : 1);
+        const double ee = (double)gd.ncand * (double)si.n;
+        c->stats.segments_max = std::max<int64_t>(c->stats.segments_max, g.P);
+        if (g.P > 1) {
+            const int64_t lam_n = (int64_t)tiles * (g.P + 1);
+            const int64_t tbl_n = (int64_t)g.P * tiles * WAVE * KMAX;
+            if ((rc = ensure(c, c->lam, (size_t)lam_n * sizeof(int)))) return rc;
+            if ((rc = ensure(c, c->tbl, (size_t)tbl_n * sizeof(int2)))) return rc;
+            if ((rc = ensure(c, c->flags, (size_t)tiles * WAVE * sizeof(int)))) return rc;
+            g.lam = P<int>(c->lam);
+            g.tbl = P<int2>(c->tbl);
+            g.flags = P<int>(c->flags);
+            {
+                KTimer kt(c, "plan", 0);
+                launch_fill(g.flags, 0, (int64_t)tiles * WAVE, s);
+                launch_plan(ticks, si.n, P<int>(c->tileW) + gd.tile_base, tiles, g.P,
+                            P<int>(c->lam), s);
+            }
+            {
+                KTimer kt(c, kname, ee);
+                launch_map(N, exact, dcls, g, s);
+            }
+            {
+                const bool tree = c->param[FE_PARAM_CONCAT_TREE] && g.P >= 16;
+                KTimer kt(c, tree ? "concat_tree" : "concat_seq", 0);
+                launch_concat(g, tree, s);
+            }
+            {
+                KTimer kt(c, "fixup", 0);
+                launch_fixup(N, exact, dcls, g, s);
+            }
+        } else {
+            KTimer kt(c, kname, ee);
+            launch_map(N, exact, dcls, g, s);
+        }
+        HIPCHK(c, hipGetLastError());
+    }
+    return FE_OK;
+}
+
 // One counting pass (relaxed or exact) over candidates cin (optionally the
 // subset sel[0..*nsel) of them), writing out[m] for every counted m.
 int run_pass(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, int num_types,
@@ -300,63 +379,12 @@ int run_pass(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, 
                             P<int>(c->orig), P<int>(c->tileW), s);
     }
 
-    for (int k = 0; k < NKEYS; ++k) {
-        if (!cnt[k]) continue;
-        const int N = k / NDCLS + 1, dcls = k % NDCLS;
-        const int tiles = (cnt[k] + WAVE - 1) / WAVE;
-        MapGroup g;
-        g.ids = ids;
-        g.ticks = ticks;
-        g.n = si.n;
-        g.pk = P<int>(c->pk) + lay.rec_base[k];
-        g.orig = P<int>(c->orig) + (int64_t)lay.tile_base[k] * WAVE;
-        g.out = out;
-        g.status = P<int>(c->status);
-        g.tiles = tiles;
-        g.lam = nullptr;
-        g.tbl = nullptr;
-        g.flags = nullptr;
-        g.P = choose_P(c, tiles, si, wmax[k]);
-        c->stats.map_launches++;
-        char kname[40];
-        snprintf(kname, sizeof kname, "map_%s_n%d_d%d", exact ? "exact" : "relaxed", N,
-                 exact ? dcls_depth(dcls) : 1);
-        const double ee = (double)cnt[k] * (double)si.n;
-        c->stats.segments_max = std::max<int64_t>(c->stats.segments_max, g.P);
-        if (g.P > 1) {
-            const int64_t lam_n = (int64_t)tiles * (g.P + 1);
-            const int64_t tbl_n = (int64_t)g.P * tiles * WAVE * KMAX;
-            if ((rc = ensure(c, c->lam, (size_t)lam_n * sizeof(int)))) return rc;
-            if ((rc = ensure(c, c->tbl, (size_t)tbl_n * sizeof(int2)))) return rc;
-            if ((rc = ensure(c, c->flags, (size_t)tiles * WAVE * sizeof(int)))) return rc;
-            g.lam = P<int>(c->lam);
-            g.tbl = P<int2>(c->tbl);
-            g.flags = P<int>(c->flags);
-            {
-                KTimer kt(c, "plan", 0);
-                launch_fill(g.flags, 0, (int64_t)tiles * WAVE, s);
-                launch_plan(ticks, si.n, P<int>(c->tileW) + lay.tile_base[k], tiles, g.P,
-                            P<int>(c->lam), s);
-            }
-            {
-                KTimer kt(c, kname, ee);
-                launch_map(N, exact, dcls, g, s);
-            }
-            {
-                const bool tree = c->param[FE_PARAM_CONCAT_TREE] && g.P >= 16;
-                KTimer kt(c, tree ? "concat_tree" : "concat_seq", 0);
-                launch_concat(g, tree, s);
-            }
-            {
-                KTimer kt(c, "fixup", 0);
-                launch_fixup(N, exact, dcls, g, s);
-            }
-        } else {
-            KTimer kt(c, kname, ee);
-            launch_map(N, exact, dcls, g, s);
-        }
-        HIPCHK(c, hipGetLastError());
-    }
+    std::vector<GroupDesc> groups;
+    for (int k = 0; k < NKEYS; ++k)
+        if (cnt[k])
+            groups.push_back(GroupDesc{k, (cnt[k] + WAVE - 1) / WAVE, lay.tile_base[k],
+                                       (int64_t)lay.rec_base[k], wmax[k], (int64_t)cnt[k]});
+    return launch_groups(c, ids, ticks, si, groups, exact, out);
     return FE_OK;
 }
 
@@ -440,10 +468,26 @@ int two_pass_impl(fe_ctx *c, const int32_t *ids, const int32_t *ticks, const Str
         KTimer kt(c, "compact", 0);
         launch_compact(upper, M, theta, exact, P<int>(c->sel), P<int>(c->nsel), s);
     }
-    if (si.n > 0 &&
-        (rc = run_pass(c, ids, ticks, si, num_types, cin, P<int>(c->sel), P<int>(c->nsel), M,
-                       true, exact)))
-        return rc;
+    if (si.n > 0) {
+        int ns = 0;
+        HIPCHK(c, hipMemcpyAsync(c->host, P<int>(c->nsel), sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        ns = c->host[0];
+        if ((int64_t)ns * 2 > (int64_t)M) {
+            // most candidates survive: count them all in their input order
+            // (which keeps tiles of join siblings together) and keep the
+            // survivors' counts
+            if ((rc = ensure(c, c->small, (size_t)M * sizeof(int)))) return rc;
+            if ((rc = run_pass(c, ids, ticks, si, num_types, cin, nullptr, nullptr, M, true,
+                               P<int>(c->small))))
+                return rc;
+            launch_select(upper, P<int>(c->small), M, theta, exact, s);
+        } else if (ns > 0) {
+            if ((rc = run_pass(c, ids, ticks, si, num_types, cin, P<int>(c->sel), P<int>(c->nsel),
+                               M, true, exact)))
+                return rc;
+        }
+    }
     if (nsurv_out)
         HIPCHK(c, hipMemcpyAsync(nsurv_out, P<int>(c->nsel), sizeof(int), hipMemcpyDeviceToDevice,
                                  s));
@@ -719,6 +763,145 @@ struct LevelOut {
     double gen_ms, count_ms;
 };
 
+// Host-side tiling of a level's candidates (all of size m) for the Map
+// kernels, in the packed tile layout the device grouping produces:
+// candidates are grouped by list-depth class; inside a group, maximal runs
+// of join siblings (same first m-1 types, consecutive in generation order)
+// fill whole tiles, so those waves take the shared-prefix path; a run's
+// remainder of at least half a tile gets a padded tile of its own, shorter
+// remainders are packed together.
+struct HostPack {
+    std::vector<int> rec, orig, tileW;
+    std::vector<GroupDesc> groups;
+    int tiles = 0;
+};
+
+int host_dcls(const int *k, int m, bool exact)
+{
+    if (!exact) return 0;
+    int bound = 1;
+    for (int j = 0; j < m - 1; ++j) {
+        const int lo = k[3 * j + 1], hi = k[3 * j + 2];
+        bound = std::max(bound, hi / (hi - lo + 1) + 1);
+    }
+    return bound <= 1 ? 0 : bound <= 2 ? 1 : bound <= 4 ? 2 : 3;
+}
+
+void host_pack(const Episodes &C, const std::vector<int> &order, bool exact, HostPack &hp)
+{
+    const int m = C.m;
+    const int ri = rec_ints(m);
+    hp.rec.clear();
+    hp.orig.clear();
+    hp.tileW.clear();
+    hp.groups.clear();
+    hp.tiles = 0;
+    std::vector<int> byc[NDCLS];
+    for (int i : order) byc[host_dcls(C.at(i), m, exact)].push_back(i);
+    auto same_prefix = [&](int a, int b) {
+        const int *x = C.at(a), *y = C.at(b);
+        for (int j = 0; j < m - 1; ++j)
+            if (x[3 * j] != y[3 * j]) return false;
+        return true;
+    };
+    std::vector<int> lanes;  // candidate per lane slot, -1 = padding
+    for (int cls = 0; cls < NDCLS; ++cls) {
+        const std::vector<int> &v = byc[cls];
+        if (v.empty()) continue;
+        lanes.clear();
+        std::vector<int> mixed;
+        size_t i = 0;
+        while (i < v.size()) {
+            size_t j = i + 1;
+            while (j < v.size() && same_prefix(v[i], v[j])) ++j;
+            size_t r = j - i;
+            size_t q = i;
+            while (r >= (size_t)WAVE) {
+                lanes.insert(lanes.end(), v.begin() + q, v.begin() + q + WAVE);
+                q += WAVE;
+                r -= WAVE;
+            }
+            if (r >= (size_t)WAVE / 2) {
+                lanes.insert(lanes.end(), v.begin() + q, v.begin() + j);
+                lanes.insert(lanes.end(), WAVE - r, -1);
+            } else {
+                mixed.insert(mixed.end(), v.begin() + q, v.begin() + j);
+            }
+            i = j;
+        }
+        lanes.insert(lanes.end(), mixed.begin(), mixed.end());
+        if (lanes.size() % WAVE) lanes.insert(lanes.end(), WAVE - lanes.size() % WAVE, -1);
+        const int tiles = (int)(lanes.size() / WAVE);
+        GroupDesc gd{(m - 1) * NDCLS + cls, tiles, hp.tiles, (int64_t)hp.rec.size(), 0,
+                     (int64_t)v.size()};
+        const size_t rec0 = hp.rec.size(), orig0 = hp.orig.size(), tw0 = hp.tileW.size();
+        hp.rec.resize(rec0 + (size_t)tiles * ri);
+        hp.orig.resize(orig0 + (size_t)tiles * WAVE);
+        hp.tileW.resize(tw0 + tiles);
+        auto fill_tiles = [&](int t0, int t1) {
+            for (int t = t0; t < t1; ++t) {
+                int *rec = hp.rec.data() + rec0 + (size_t)t * ri;
+                int W = 0;
+                for (int l = 0; l < WAVE; ++l) {
+                    const int idx = lanes[(size_t)t * WAVE + l];
+                    hp.orig[orig0 + (size_t)t * WAVE + l] = idx;
+                    if (idx < 0) {
+                        for (int k = 0; k < m; ++k) rec[k * WAVE + l] = -1;
+                        for (int k = 0; k < m - 1; ++k) {
+                            rec[(m + k) * WAVE + l] = 0;
+                            rec[(2 * m - 1 + k) * WAVE + l] = 0;
+                        }
+                        continue;
+                    }
+                    const int *key = C.at(idx);
+                    int w = 0;
+                    for (int k = 0; k < m; ++k) rec[k * WAVE + l] = key[3 * k];
+                    for (int k = 0; k < m - 1; ++k) {
+                        rec[(m + k) * WAVE + l] = key[3 * k + 1];
+                        rec[(2 * m - 1 + k) * WAVE + l] = key[3 * k + 2];
+                        w += key[3 * k + 2];
+                    }
+                    W = std::max(W, w);
+                }
+                hp.tileW[tw0 + t] = W;
+            }
+        };
+        const int nth = (int)std::min<int64_t>(16, std::max<int64_t>(1, tiles / 2048));
+        if (nth <= 1) {
+            fill_tiles(0, tiles);
+        } else {
+            std::vector<std::thread> th;
+            for (int q = 0; q < nth; ++q)
+                th.emplace_back(fill_tiles, (int)((int64_t)tiles * q / nth),
+                                (int)((int64_t)tiles * (q + 1) / nth));
+            for (auto &t : th) t.join();
+        }
+        for (int t = 0; t < tiles; ++t) gd.wmax = std::max(gd.wmax, hp.tileW[tw0 + t]);
+        hp.tiles += tiles;
+        hp.groups.push_back(gd);
+    }
+}
+
+int upload_pack(fe_ctx *c, const HostPack &hp)
+{
+    int rc;
+    hipStream_t s = c->stream;
+    if ((rc = ensure(c, c->pk, std::max<size_t>(hp.rec.size(), 1) * sizeof(int)))) return rc;
+    if ((rc = ensure(c, c->orig, std::max<size_t>(hp.orig.size(), 1) * sizeof(int)))) return rc;
+    if ((rc = ensure(c, c->tileW, std::max<size_t>(hp.tileW.size(), 1) * sizeof(int)))) return rc;
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (!hp.rec.empty())
+        HIPCHK(c, hipMemcpyAsync(P<int>(c->pk), hp.rec.data(), hp.rec.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, s));
+    if (!hp.orig.empty())
+        HIPCHK(c, hipMemcpyAsync(P<int>(c->orig), hp.orig.data(), hp.orig.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, s));
+    if (!hp.tileW.empty())
+        HIPCHK(c, hipMemcpyAsync(P<int>(c->tileW), hp.tileW.data(),
+                                 hp.tileW.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    return FE_OK;
+}
+
 }  // namespace
 
 extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int64_t n,
@@ -786,47 +969,43 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         if (M == 0) break;
         if (M >= (size_t)1 << 31 || M * level >= (size_t)1 << 31)
             return fail(c, FE_ENOMEM, "level %d has too many candidates (%zu)", level, M);
-        // device candidate table in the fe_count layout
-        const int w = 3 * level - 2;
-        std::vector<int> ty(M * level), lo(M * (level - 1)), hi(M * (level - 1));
-        for (size_t i = 0; i < M; ++i) {
-            const int *k = C.at(i);
-            for (int j = 0; j < level; ++j) ty[i * level + j] = k[3 * j];
-            for (int j = 0; j < level - 1; ++j) {
-                lo[i * (level - 1) + j] = k[3 * j + 1];
-                hi[i * (level - 1) + j] = k[3 * j + 2];
-            }
-        }
-        (void)w;
         const double gen_ms = now_ms() - t0;
         t0 = now_ms();
-        if ((rc = ensure(c, c->mtypes, ty.size() * sizeof(int)))) return rc;
-        if ((rc = ensure(c, c->mlen, M * sizeof(int)))) return rc;
-        if ((rc = ensure(c, c->mlo, lo.size() * sizeof(int)))) return rc;
-        if ((rc = ensure(c, c->mhi, hi.size() * sizeof(int)))) return rc;
         if ((rc = ensure(c, c->mup, 2 * M * sizeof(int)))) return rc;
         if ((rc = ensure(c, c->mex, 2 * M * sizeof(int)))) return rc;
         if ((rc = ensure(c, c->msel, M * sizeof(int)))) return rc;
         if ((rc = ensure(c, c->mn, 4 * sizeof(int)))) return rc;
-        HIPCHK(c, hipMemcpyAsync(P<int>(c->mtypes), ty.data(), ty.size() * sizeof(int),
-                                 hipMemcpyHostToDevice, s));
-        HIPCHK(c, hipMemcpyAsync(P<int>(c->mlo), lo.data(), lo.size() * sizeof(int),
-                                 hipMemcpyHostToDevice, s));
-        HIPCHK(c, hipMemcpyAsync(P<int>(c->mhi), hi.data(), hi.size() * sizeof(int),
-                                 hipMemcpyHostToDevice, s));
-        launch_fill(P<int>(c->mlen), level, (int64_t)M, s);
         int *up = P<int>(c->mup), *ex = P<int>(c->mex);
-        CandIn cin{P<int>(c->mtypes), P<int>(c->mlen), P<int>(c->mlo), P<int>(c->mhi), level};
-        if ((rc = two_pass_impl(c, ids, ticks, si, num_types, cin, (int)M, theta, up, ex,
-                                P<int>(c->mn) + 1)))
-            return rc;
+        // pass 1 (Algorithm 3) over every candidate
+        std::vector<int> order(M);
+        for (size_t i = 0; i < M; ++i) order[i] = (int)i;
+        HostPack hp;
+        host_pack(C, order, false, hp);
+        if ((rc = upload_pack(c, hp))) return rc;
+        if ((rc = launch_groups(c, ids, ticks, si, hp.groups, false, up))) return rc;
+        // elimination (Algorithm 4): survivors have upper >= theta
+        std::vector<int> uph(M);
+        HIPCHK(c, hipMemcpyAsync(uph.data(), up, M * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        order.clear();
+        for (size_t i = 0; i < M; ++i)
+            if (uph[i] >= theta) order.push_back((int)i);
+        const int64_t nsurv = (int64_t)order.size();
+        // pass 2 (Algorithm 1) over the survivors; the others keep -1
+        launch_fill(ex, -1, (int64_t)M, s);
+        if (nsurv > 0) {
+            host_pack(C, order, true, hp);
+            if ((rc = upload_pack(c, hp))) return rc;
+            if ((rc = launch_groups(c, ids, ticks, si, hp.groups, true, ex))) return rc;
+        }
         // frequent = exact >= theta
         launch_fill(P<int>(c->mn), 0, 1, s);
         launch_compact(ex, (int)M, theta, nullptr, P<int>(c->msel), P<int>(c->mn), s);
         launch_gather2(up, ex, P<int>(c->msel), P<int>(c->mn), (int)M, up + M, ex + M, s);
         int cnts[2];
-        HIPCHK(c, hipMemcpyAsync(cnts, P<int>(c->mn), 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(cnts, P<int>(c->mn), sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
+        cnts[1] = (int)nsurv;
         const int nf = cnts[0];
         std::vector<int> fsel(nf), fup(nf), fex(nf);
         if (nf > 0) {

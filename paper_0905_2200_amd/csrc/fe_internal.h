@@ -9,7 +9,7 @@ namespace fe {
 
 constexpr int WAVE = 64;
 constexpr int NMAX = 8;          // largest episode size
-constexpr int KMAX = 4;          // slot-table entries kept per (candidate, segment)
+constexpr int KMAX = 16;         // slot-table entries kept per (candidate, segment)
 constexpr int NDCLS = 4;         // list-depth classes of the exact machine: 1,2,4,8 windows
 constexpr int NKEYS = NMAX * NDCLS;
 constexpr int TICK_LIMIT = 1 << 30;
@@ -66,6 +66,7 @@ void launch_concat(const MapGroup &g, bool tree, hipStream_t s);
 void launch_fixup(int N, bool exact, int dcls, const MapGroup &g, hipStream_t s);
 void launch_compact(const int *vals, int M, int theta, int *pruned_out,
                     int *sel, int *nsel, hipStream_t s);
+void launch_select(const int *vals, const int *src, int M, int theta, int *out, hipStream_t s);
 void launch_gather2(const int *a, const int *b, const int *sel, const int *nsel, int M,
                     int *out_a, int *out_b, hipStream_t s);
 void launch_histogram(const int *ids, int n, int num_types, int *hist,

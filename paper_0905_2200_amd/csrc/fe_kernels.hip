@@ -277,53 +277,51 @@ __global__ void k_concat_seq(MapGroup g)
 }
 
 // One wave per candidate: lane l composes a contiguous chunk of segments
-// sequentially, then the 64 chunk tables are composed by a shuffle tree.
+// sequentially, then the 64 chunk tables are composed pairwise in log2(64)
+// steps through LDS (lane l takes lane l+s's table at the slot its own
+// entries exit into).  Every wave of the block takes part in the barriers.
 __global__ __launch_bounds__(WAVE *WPB) void k_concat_tree(MapGroup g)
 {
+    __shared__ int sc[WPB][WAVE][KMAX];
+    __shared__ int sx[WPB][WAVE][KMAX];
     const int lane = __lane_id();
-    const int c = uniform_u(blockIdx.x * WPB + (threadIdx.x >> 6));
-    if (c >= g.tiles * WAVE) return;
-    const int o = g.orig[c];
-    if (o < 0 || g.flags[c]) return;
+    const int wv = threadIdx.x >> 6;
+    const int c = uniform_u(blockIdx.x * WPB + wv);
+    const bool have = c < g.tiles * WAVE && g.orig[c] >= 0 && !g.flags[c];
     const int P = g.P;
     const int cs = (P + WAVE - 1) / WAVE;
     const int p0 = lane * cs;
     const int p1 = p0 + cs < P ? p0 + cs : P;
     const int64_t stride = (int64_t)g.tiles * WAVE * KMAX;
-    const int2 *t = g.tbl + (int64_t)c * KMAX;
+    const int2 *t = g.tbl + (int64_t)(have ? c : 0) * KMAX;
     int tc[KMAX], tx[KMAX];
 #pragma unroll
     for (int j = 0; j < KMAX; ++j) {
         int x = j, tot = 0;
-        for (int p = p0; p < p1; ++p) {
-            const int2 v = t[p * stride + x];
-            tot += v.x;
-            x = clampk(v.y);
-        }
+        if (have)
+            for (int p = p0; p < p1; ++p) {
+                const int2 v = t[p * stride + x];
+                tot += v.x;
+                x = clampk(v.y);
+            }
         tc[j] = tot;
         tx[j] = x;
     }
-#pragma unroll
     for (int s = 1; s < WAVE; s <<= 1) {
-        int pc[KMAX], px[KMAX];
 #pragma unroll
-        for (int j = 0; j < KMAX; ++j) {
-            pc[j] = __shfl(tc[j], lane + s < WAVE ? lane + s : lane);
-            px[j] = __shfl(tx[j], lane + s < WAVE ? lane + s : lane);
-        }
+        for (int j = 0; j < KMAX; ++j) { sc[wv][lane][j] = tc[j]; sx[wv][lane][j] = tx[j]; }
+        __syncthreads();
         if ((lane & (2 * s - 1)) == 0 && lane + s < WAVE) {
 #pragma unroll
             for (int j = 0; j < KMAX; ++j) {
-                int ac = 0, ax = 0;
-#pragma unroll
-                for (int q = 0; q < KMAX; ++q)
-                    if (tx[j] == q) { ac = pc[q]; ax = px[q]; }
-                tc[j] += ac;
-                tx[j] = ax;
+                const int q = tx[j];
+                tc[j] += sc[wv][lane + s][q];
+                tx[j] = sx[wv][lane + s][q];
             }
         }
+        __syncthreads();
     }
-    if (lane == 0) g.out[o] = tc[0];
+    if (have && lane == 0) g.out[g.orig[c]] = tc[0];
 }
 
 void launch_concat(const MapGroup &g, bool tree, hipStream_t s)
@@ -354,6 +352,19 @@ void launch_compact(const int *vals, int M, int theta, int *pruned_out, int *sel
     if (M <= 0) return;
     hipLaunchKernelGGL(k_compact, dim3((M + 255) / 256), dim3(256), 0, s, vals, M, theta,
                        pruned_out, sel, nsel);
+}
+
+// out[m] = vals[m] >= theta ? src[m] : -1
+__global__ void k_select(const int *vals, const int *src, int M, int theta, int *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) out[i] = vals[i] >= theta ? src[i] : -1;
+}
+
+void launch_select(const int *vals, const int *src, int M, int theta, int *out, hipStream_t s)
+{
+    if (M <= 0) return;
+    hipLaunchKernelGGL(k_select, dim3((M + 255) / 256), dim3(256), 0, s, vals, src, M, theta, out);
 }
 
 // out_a[i] = a[sel[i]], out_b[i] = b[sel[i]] for i < *nsel

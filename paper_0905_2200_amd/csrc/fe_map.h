@@ -7,6 +7,10 @@
 // tile of 64 candidates over one segment.  Every lane reads the same event,
 // so events come through scalar loads in the constant address space (one
 // SMEM fetch serves 64 machines) and machine state stays in VGPRs.
+// Candidates produced by the level-wise join arrive in tiles whose first
+// N-1 node types are the same in every lane; such waves take a path where
+// those nodes are tested with scalar compares and only the last node is
+// per lane.
 //
 // Counting semantics: for each event, nodes are visited from N down to 1
 // against the state before the event; a node-i match whose hop test passes
@@ -28,10 +32,13 @@
 // only at events of type E_(N).  On segment [L, R) the true machine
 // therefore behaves like a fresh machine started right after max(r, lam-1)
 // (r = last completion before L, lam = first index with tick >= t_L - W).
-// The restart points ("slots") are lam-1 and each E_(N) event in [lam, L);
-// the Map step runs one machine per slot and writes, per slot, the
-// completions it counts in [L, R) and the slot it leaves the next segment
-// in.  Concatenate composes those tables.
+// The restart points ("slots") are lam-1 (slot 0) and the j-th E_(N) event
+// in [lam, L) (slot j).  The Map step runs one machine per slot and writes,
+// per slot, the completions it counts in [L, R) and the slot it leaves the
+// next segment in; Concatenate composes those tables.  Two machines that
+// complete at the same event are identical from then on, so a slot machine
+// stops at its first completion shared with the slot-0 machine and takes
+// the rest of the result from it.
 #pragma once
 
 #include "fe_internal.h"
@@ -40,6 +47,7 @@ namespace fe {
 
 typedef const __attribute__((address_space(4))) int *cptr;
 static constexpr int EMPTY = 0x7fffffff;
+static constexpr int QREC = 4;  // slot-0 completions remembered for merging
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -59,6 +67,15 @@ template <int N> __device__ __forceinline__ void load_cand(Cand<N> &c, const int
         c.hi[k] = rec[(2 * N - 1 + k) * WAVE + lane];
     }
 }
+
+// Types of nodes 0..N-2 shared by every valid lane (wave-uniform values),
+// and a 64-bit filter with bit (type & 63) set for each of them: an event
+// whose bit is clear matches none of those nodes.
+template <int N> struct Prefix {
+    int ty[N > 1 ? N - 1 : 1];
+    unsigned long long mask;
+    __device__ __forceinline__ bool maybe(int e) const { return (mask >> (e & 63)) & 1ull; }
+};
 
 template <int N> struct Relaxed {
     int dl[N > 1 ? N - 1 : 1];
@@ -80,6 +97,23 @@ template <int N> struct Relaxed {
             }
             const bool m0 = on & (e == c.ty[0]);
             dl[0] = m0 ? t + c.hi[0] : dl[0];
+            return comp;
+        }
+    }
+    // Nodes 0..N-2 have wave-uniform types u.ty: scalar tests, rare updates.
+    __device__ __forceinline__ bool step_u(int e, int t, const Cand<N> &c, const Prefix<N> &u,
+                                           int *)
+    {
+        if constexpr (N == 1) {
+            return e == c.ty[0];
+        } else {
+            const bool comp = (e == c.ty[N - 1]) & (t <= dl[N - 2]);
+            if (__builtin_expect(u.maybe(e), 0)) {
+#pragma unroll
+                for (int i = N - 2; i >= 1; --i)
+                    if (e == u.ty[i]) dl[i] = t <= dl[i - 1] ? t + c.hi[i] : dl[i];
+                if (e == u.ty[0]) dl[0] = t + c.hi[0];
+            }
             return comp;
         }
     }
@@ -149,10 +183,31 @@ template <int N, int D> struct Exact {
             return comp;
         }
     }
+    __device__ __forceinline__ bool step_u(int e, int t, const Cand<N> &c, const Prefix<N> &u,
+                                           int *status)
+    {
+        if constexpr (N == 1) {
+            return e == c.ty[0];
+        } else {
+            const bool comp = (e == c.ty[N - 1]) & hit(N - 2, t);
+            if (__builtin_expect(u.maybe(e), 0)) {
+#pragma unroll
+                for (int i = N - 2; i >= 1; --i)
+                    if (e == u.ty[i])
+                        if (hit(i - 1, t)) push(i, t, c.lo[i], c.hi[i], status);
+                if (e == u.ty[0]) push(0, t, c.lo[0], c.hi[0], status);
+            }
+            return comp;
+        }
+    }
 };
 
 template <int N, bool EXACT, int D> struct MachineOf { typedef Relaxed<N> type; };
 template <int N, int D> struct MachineOf<N, true, D> { typedef Exact<N, D> type; };
+
+template <int N, bool EXACT, int D> struct Unroll {
+    static constexpr int U = EXACT ? (D >= 4 || N >= 6 ? 2 : 4) : 8;
+};
 
 // Stream [b, e) (wave-uniform bounds) through scalar loads, U events per
 // fetch, calling f(id, tick, index) in stream order.
@@ -171,71 +226,156 @@ __device__ __forceinline__ void for_events(cptr ids, cptr ticks, int b, int e, F
     for (; i < e; ++i) f(ids[i], ticks[i], i);
 }
 
-// One machine run with the Map step's bookkeeping.  GUARD: lanes start at
-// their own index `start` (slot machines) and only lanes with `act` run.
-template <int N, bool EXACT, int D, bool GUARD> struct Run {
-    static constexpr int U = EXACT ? (D >= 4 || N >= 6 ? 2 : 4) : 8;
+// The slot-0 machine of a segment (or the only machine when P = 1).
+template <int N, bool EXACT, int D> struct MainRun {
+    static constexpr int U = Unroll<N, EXACT, D>::U;
     typename MachineOf<N, EXACT, D>::type m;
-    int cnt = 0;    // completions counted
+    int cnt = 0;    // completions counted (index >= L)
     int lastx = 0;  // exit slot in the next segment implied by the last completion
     int nx = 0;     // E_(N) events seen at index >= lamn (exit numbering)
-    int start = 0;
-    bool act = true;
-    int ks = 0, s0 = -1, s1 = -1, s2 = -1;  // look-back E_(N) positions (slots 1..3)
+    int ks = 0;     // E_(N) events in the look-back [lam, L)
+    int q = 0;      // completions seen; the first QREC are kept for merging
+    int ci[QREC], ck[QREC];
 
-    __device__ __forceinline__ bool on(int idx) const
+    __device__ __forceinline__ void note(int idx)
     {
-        if constexpr (GUARD) return act & (idx >= start);
-        else return true;
+#pragma unroll
+        for (int k = 0; k < QREC; ++k) {
+            ci[k] = q == k ? idx : ci[k];
+            ck[k] = q == k ? cnt : ck[k];
+        }
+        ++q;
     }
 
-    // Bulk of a segment: count every completion; no exit bookkeeping (only
-    // called on indices below the next segment's look-back).
-    __device__ void body(cptr ids, cptr ticks, int b, int e, const Cand<N> &c, int *status)
+    // Bulk of a segment (indices below the next look-back): count every
+    // completion.  UNI: the tile shares the types of nodes 0..N-2.
+    template <bool UNI, bool NOTE>
+    __device__ void body(cptr ids, cptr ticks, int b, int e, const Cand<N> &c,
+                         const Prefix<N> &u, int *status)
     {
         if (uniform(b) >= uniform(e)) return;
         for_events<U>(ids, ticks, b, e, [&](int ev, int t, int idx) {
-            if (m.step(ev, t, c, on(idx), status)) {
+            bool comp;
+            if constexpr (UNI) comp = m.step_u(ev, t, c, u, status);
+            else comp = m.step(ev, t, c, true, status);
+            if (comp) {
                 m.reset();
                 ++cnt;
                 lastx = 0;
+                if constexpr (NOTE) note(idx);
             }
         });
     }
 
-    // Edges of a segment (look-back and the next segment's look-back):
-    // completions count only at idx >= L, an exit slot is numbered at
-    // idx >= lamn, and with rec the E_(N) events before L are recorded.
-    __device__ void edge(cptr ids, cptr ticks, int b, int e, int L, int lamn, bool rec,
-                         const Cand<N> &c, int *status)
+    // Look-back and tail of a segment: completions count only at idx >= L,
+    // exit slots are numbered at idx >= lamn, look-back E_(N) events are
+    // counted into ks.
+    __device__ void edge(cptr ids, cptr ticks, int b, int e, int L, int lamn, const Cand<N> &c,
+                         int *status)
     {
         if (uniform(b) >= uniform(e)) return;
         for_events<U>(ids, ticks, b, e, [&](int ev, int t, int idx) {
-            const bool o = on(idx);
-            const bool comp = m.step(ev, t, c, o, status);
+            const bool comp = m.step(ev, t, c, true, status);
             const bool nx_on = idx >= lamn;
             if (comp) {
                 m.reset();
                 cnt += idx >= L ? 1 : 0;
                 lastx = nx_on ? nx + 1 : 0;
+                note(idx);
             }
-            const bool isN = o & (ev == c.ty[N - 1]);
+            const bool isN = ev == c.ty[N - 1];
             nx += (nx_on & isN) ? 1 : 0;
-            if (rec & (idx < L) & isN) {
-                s0 = ks == 0 ? idx : s0;
-                s1 = ks == 1 ? idx : s1;
-                s2 = ks == 2 ? idx : s2;
-                ++ks;
-            }
+            ks += ((idx < L) & isN) ? 1 : 0;
         });
     }
 };
+
+// Slot j >= 1: a fresh machine started right after the j-th E_(N) event of
+// the look-back; stops once a completion coincides with one of the slot-0
+// machine's remembered completions.
+template <int N, bool EXACT, int D>
+__device__ void slot_pass(cptr ids, cptr ticks, int lam, int L, int R, int lamn, int j,
+                          bool act, const Cand<N> &c, const MainRun<N, EXACT, D> &mr,
+                          int *status, int &out_cnt, int &out_x)
+{
+    constexpr int U = Unroll<N, EXACT, D>::U;
+    typename MachineOf<N, EXACT, D>::type m;
+    m.reset();
+    int cnt = 0, lastx = 0, nx = 0, seen = 0;
+    bool started = false, live = act;
+    int i = uniform(lam);
+    const int e = uniform(R);
+    auto f = [&](int ev, int t, int idx) {
+        const bool isN = ev == c.ty[N - 1];
+        const bool nx_on = idx >= lamn;
+        const bool comp = m.step(ev, t, c, live & started, status);
+        if (comp) {
+            m.reset();
+            cnt += idx >= L ? 1 : 0;
+            lastx = nx_on ? nx + 1 : 0;
+            // merge with the slot-0 machine at a shared completion
+            int hitk = -1;
+#pragma unroll
+            for (int k = 0; k < QREC; ++k) hitk = (k < mr.q && mr.ci[k] == idx) ? k : hitk;
+            if (hitk >= 0) {
+                int ckk = 0;
+#pragma unroll
+                for (int k = 0; k < QREC; ++k) ckk = k == hitk ? mr.ck[k] : ckk;
+                cnt += mr.cnt - ckk;
+                lastx = mr.lastx;
+                live = false;
+            }
+        }
+        const bool starts = live & !started & isN & (idx < L) & (seen + 1 == j);
+        if (starts) {
+            started = true;
+            lastx = nx_on ? nx + 1 : 0;
+        }
+        seen += (isN & (idx < L)) ? 1 : 0;
+        nx += (isN & nx_on) ? 1 : 0;
+    };
+    for (; i + U <= e; i += U) {
+        if (__ballot(live) == 0) break;
+        int ev[U], tv[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) { ev[k] = ids[i + k]; tv[k] = ticks[i + k]; }
+#pragma unroll
+        for (int k = 0; k < U; ++k) f(ev[k], tv[k], i + k);
+    }
+    for (; i < e; ++i) {
+        if (__ballot(live) == 0) break;
+        f(ids[i], ticks[i], i);
+    }
+    out_cnt = cnt;
+    out_x = lastx;
+}
+
+// true when every valid lane has the same types in nodes 0..N-2
+template <int N>
+__device__ __forceinline__ bool shared_prefix(const Cand<N> &c, bool valid, Prefix<N> &u)
+{
+    if constexpr (N == 1) {
+        return false;
+    } else {
+        const unsigned long long vm = __ballot(valid);
+        if (vm == 0) return false;
+        const int first = __ffsll((long long)vm) - 1;
+        bool same = true;
+        u.mask = 0;
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) {
+            u.ty[k] = uniform(__shfl(c.ty[k], first));
+            same &= __ballot(valid & (c.ty[k] != u.ty[k])) == 0;
+            u.mask |= 1ull << (u.ty[k] & 63);
+        }
+        return same;
+    }
+}
 
 template <int N, bool EXACT, int D>
 __global__ __launch_bounds__(WAVE *WPB) void k_map(const int *__restrict__ ids_,
                                                    const int *__restrict__ ticks_, MapGroup g)
 {
-    static_assert(KMAX == 4, "slot recording holds KMAX-1 = 3 positions");
     cptr ids = (cptr)ids_;
     cptr ticks = (cptr)ticks_;
     const int lane = __lane_id();
@@ -248,11 +388,14 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map(const int *__restrict__ ids_,
 
     Cand<N> cd;
     load_cand<N>(cd, g.pk + (int64_t)tile * rec_ints(N), lane);
+    Prefix<N> u;
+    const bool uni = shared_prefix<N>(cd, o >= 0, u);
 
-    Run<N, EXACT, D, false> r;
+    MainRun<N, EXACT, D> r;
     r.m.reset();
     if (P == 1) {
-        r.body(ids, ticks, 0, g.n, cd, g.status);
+        if (uni) r.template body<true, false>(ids, ticks, 0, g.n, cd, u, g.status);
+        else r.template body<false, false>(ids, ticks, 0, g.n, cd, u, g.status);
         if (o >= 0) g.out[o] = r.cnt;
         return;
     }
@@ -267,45 +410,33 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map(const int *__restrict__ ids_,
     int2 *tb = g.tbl + ((int64_t)p * tiles * WAVE + c) * KMAX;
 
     // slot 0: the last completion before L lies before lam
-    r.edge(ids, ticks, lam, L, L, lamn, true, cd, g.status);
-    r.body(ids, ticks, L, xl, cd, g.status);
-    r.edge(ids, ticks, xl, R, L, lamn, false, cd, g.status);
+    for (int k = 0; k < QREC; ++k) { r.ci[k] = -1; r.ck[k] = 0; }
+    r.edge(ids, ticks, lam, L, L, lamn, cd, g.status);
+    if (uni) r.template body<true, true>(ids, ticks, L, xl, cd, u, g.status);
+    else r.template body<false, true>(ids, ticks, L, xl, cd, u, g.status);
+    r.edge(ids, ticks, xl, R, L, lamn, cd, g.status);
     tb[0] = make_int2(r.cnt, r.lastx < KMAX ? r.lastx : KMAX - 1);
 
-    const int ks = r.ks;
-    const bool ovf = ks > KMAX - 1;
+    const int K = r.ks + 1;  // slots of this lane
+    const bool ovf = K > KMAX;
     if (ovf && o >= 0) g.flags[c] = 1;
-    // recorded slots that lie before the next segment's look-back
-    const int fk = (ks > 0 && r.s0 < lamn) + (ks > 1 && r.s1 < lamn) + (ks > 2 && r.s2 < lamn);
-
-    // slot j: the last completion before L is the j-th E_(N) event in [lam, L)
-    for (int j = 1; j < KMAX; ++j) {
-        const bool act = !ovf && o >= 0 && ks >= j;
-        if (__ballot(act) == 0) break;
-        const int sig = j == 1 ? r.s0 : (j == 2 ? r.s1 : r.s2);
-        Run<N, EXACT, D, true> q;
-        q.m.reset();
-        q.act = act;
-        q.start = sig + 1;
-        q.nx = j - fk > 0 ? j - fk : 0;
-        q.lastx = sig >= lamn ? j - fk : 0;
-        int b = act ? sig + 1 : 0x7fffffff;
+    int kw = (ovf || o < 0) ? 1 : K;
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const int ob = __shfl_xor(b, off);
-            b = ob < b ? ob : b;
-        }
-        b = uniform(b);
-        q.edge(ids, ticks, b, L, L, lamn, false, cd, g.status);
-        const int bl = b > L ? b : L;
-        q.body(ids, ticks, bl, xl > bl ? xl : bl, cd, g.status);
-        q.edge(ids, ticks, xl > bl ? xl : bl, R, L, lamn, false, cd, g.status);
-        if (act) tb[j] = make_int2(q.cnt, q.lastx < KMAX ? q.lastx : KMAX - 1);
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int ok = __shfl_xor(kw, off);
+        kw = ok > kw ? ok : kw;
+    }
+    kw = uniform(kw);
+    for (int j = 1; j < kw; ++j) {
+        const bool act = !ovf && o >= 0 && j < K;
+        int sc = 0, sx = 0;
+        slot_pass<N, EXACT, D>(ids, ticks, lam, L, R, lamn, j, act, cd, r, g.status, sc, sx);
+        if (act) tb[j] = make_int2(sc, sx < KMAX ? sx : KMAX - 1);
     }
 }
 
 // Recount candidates flagged by the Map step (a look-back held more than
-// KMAX-1 slots) with one machine over the whole stream.
+// KMAX-1 restart slots) with one machine over the whole stream.
 template <int N, bool EXACT, int D>
 __global__ __launch_bounds__(WAVE *WPB) void k_fixup(const int *__restrict__ ids_,
                                                      const int *__restrict__ ticks_, MapGroup g)
@@ -321,12 +452,16 @@ __global__ __launch_bounds__(WAVE *WPB) void k_fixup(const int *__restrict__ ids
     if (__ballot(f) == 0) return;
     Cand<N> cd;
     load_cand<N>(cd, g.pk + (int64_t)tile * rec_ints(N), lane);
-    Run<N, EXACT, D, true> r;
-    r.m.reset();
-    r.act = f;
-    r.start = 0;
-    r.body(ids, ticks, 0, g.n, cd, g.status);
-    if (f) g.out[o] = r.cnt;
+    typename MachineOf<N, EXACT, D>::type m;
+    m.reset();
+    int cnt = 0;
+    for_events<Unroll<N, EXACT, D>::U>(ids, ticks, 0, g.n, [&](int ev, int t, int) {
+        if (m.step(ev, t, cd, f, g.status)) {
+            m.reset();
+            ++cnt;
+        }
+    });
+    if (f) g.out[o] = cnt;
 }
 
 template <int N, bool EXACT, int D> void map_n(const MapGroup &g, hipStream_t s, bool fix)
