@@ -173,6 +173,55 @@ int fe_mine(fe_ctx *ctx, const int32_t *ids, const int32_t *ticks, int64_t n,
 
 void fe_result_free(fe_result *res);
 
+/* ------------------------------------------------------------- batching */
+
+/* One recording of a batch: its stream, its own candidate table (fe_count
+ * layout, mixed episode sizes allowed), its threshold and its outputs.  All
+ * pointers are device pointers owned by the caller. */
+typedef struct fe_job {
+    const int32_t *ids, *ticks;
+    int64_t n;
+    int32_t num_types;
+    const int32_t *types, *len, *lo, *hi;
+    int32_t M, nmax;
+    int32_t theta;
+    int32_t *upper_out; /* [M] relaxed counts (Algorithm 3)                   */
+    int32_t *exact_out; /* [M] exact counts (Algorithm 1), -1 when pruned     */
+} fe_job;
+
+typedef struct fe_batch fe_batch;
+
+/* Launch shape of a batch, picked by fe_batch_autotune or set by hand. */
+typedef struct fe_batch_tuning {
+    int32_t seg_events;   /* target events per work item (segment length)    */
+    int32_t waves_per_cu; /* persistent waves launched per compute unit      */
+    double run_ms;        /* measured duration of one fe_batch_run (autotune) */
+} fe_batch_tuning;
+
+/* Plan the two-pass count (Algorithm 4) of R recordings as one batch:
+ * validates every stream and candidate table (synchronises), tiles every
+ * recording's candidates, splits long recordings into MapConcatenate
+ * segments, orders all (tile, segment) work items heaviest first, and
+ * captures one HIP graph per episode size: a persistent relaxed launch over
+ * every recording's items of that size, Concatenate, then a persistent
+ * exact launch over the survivors and Concatenate.  The streams and
+ * candidate tables must stay unchanged and valid while the batch exists. */
+int fe_batch_create(fe_ctx *ctx, int32_t R, const fe_job *jobs, fe_batch **out);
+
+/* Replay the batch's graphs on the context's stream (asynchronous). */
+int fe_batch_run(fe_batch *b);
+
+/* Time `reps` runs for each launch shape of a small grid (segment length x
+ * persistent waves per CU), keep the fastest; *best receives it.
+ * Synchronises. */
+int fe_batch_autotune(fe_batch *b, int32_t reps, fe_batch_tuning *best);
+int fe_batch_set_tuning(fe_batch *b, const fe_batch_tuning *t);
+int fe_batch_get_tuning(const fe_batch *b, fe_batch_tuning *t);
+int fe_batch_destroy(fe_batch *b);
+
+/* Convenience: create a batch, run it once, synchronise, destroy it. */
+int fe_count_batched(fe_ctx *ctx, int32_t R, const fe_job *jobs);
+
 /* Per-call statistics of the last fe_count / fe_count_two_pass / fe_mine
  * call on this context (host memory owned by ctx). */
 typedef struct fe_stats {

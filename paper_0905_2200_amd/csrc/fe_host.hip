@@ -1095,3 +1095,420 @@ extern "C" void fe_result_free(fe_result *r)
     std::free(r->levels);
     std::free(r);
 }
+
+// ====================================================================== batching
+
+struct fe_batch {
+    fe_ctx *c = nullptr;
+    std::vector<fe_job> jobs;
+    std::vector<StreamInfo> si;
+    // tiling (independent of the launch shape)
+    struct Group {
+        int job, key, t0, tiles, wmax;
+    };
+    std::vector<Group> groups;
+    std::vector<int> rec, orig, tileW;
+    int ntiles = 0;
+    fe_batch_tuning tun{32768, 16, 0.0};
+    // device
+    Buf pk, origd, tileWd, tilesd, jobsd, itemsd, listsd, lamd, tbld, flagsr, flagsx, qctr;
+    struct Level {
+        int N;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
+    };
+    std::vector<Level> levels;
+    hipStream_t cap = nullptr;
+    int ncu = 256;
+};
+
+namespace {
+
+void batch_free_graphs(fe_batch *b)
+{
+    for (auto &L : b->levels) {
+        if (L.x) (void)hipGraphExecDestroy(L.x);
+        if (L.g) (void)hipGraphDestroy(L.g);
+    }
+    b->levels.clear();
+}
+
+int batch_P(const fe_ctx *c, int n, int span, int wmax, int seg_events)
+{
+    if (n <= 1) return 1;
+    const double lb = (double)n * (double)wmax / std::max(span, 1);
+    const int64_t minseg = std::max<int64_t>(c->param[FE_PARAM_MIN_SEG_EVENTS],
+                                             (int64_t)(8.0 * lb) + 64);
+    int64_t P = (n + (int64_t)seg_events - 1) / std::max(seg_events, 1);
+    P = std::min<int64_t>(P, std::max<int64_t>(1, n / minseg));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(P, 256));
+}
+
+// Launch plan for the current tuning: per-tile descriptors, work items,
+// tile lists, device buffers and one captured graph per episode size.
+int batch_plan(fe_batch *b)
+{
+    fe_ctx *c = b->c;
+    int rc;
+    batch_free_graphs(b);
+    const int T = b->ntiles;
+    std::vector<TileDesc> td(T);
+    std::vector<int> tileN(T), tileD(T);
+    int64_t lam_off = 0, tbl_off = 0;
+    for (const auto &g : b->groups) {
+        const StreamInfo &si = b->si[g.job];
+        const int P = batch_P(c, si.n, si.span, g.wmax, b->tun.seg_events);
+        for (int t = g.t0; t < g.t0 + g.tiles; ++t) {
+            td[t].job = g.job;
+            td[t].P = P;
+            td[t].rec = 0;
+            td[t].lam = lam_off;
+            td[t].tbl = tbl_off;
+            tileN[t] = g.key / NDCLS + 1;
+            tileD[t] = g.key % NDCLS;
+            if (P > 1) {
+                lam_off += P + 1;
+                tbl_off += (int64_t)P * WAVE * KMAX;
+            }
+        }
+    }
+    // record offsets follow the packed order
+    {
+        int64_t off = 0;
+        for (const auto &g : b->groups) {
+            const int N = g.key / NDCLS + 1;
+            for (int t = g.t0; t < g.t0 + g.tiles; ++t) {
+                td[t].rec = off;
+                off += rec_ints(N);
+            }
+        }
+    }
+    // items and tile lists per level
+    std::vector<int2> items;
+    std::vector<int> lists;
+    struct LvPlan {
+        int N;
+        int64_t it_rel, n_rel;
+        int64_t it_ex[NDCLS], n_ex[NDCLS];
+        int64_t pl, npl;                   // P > 1 tiles of the level
+        int64_t pld[NDCLS], npld[NDCLS];   // P > 1 tiles per depth class
+    };
+    std::vector<LvPlan> lp;
+    for (int N = 1; N <= NMAX; ++N) {
+        std::vector<int> tl;
+        for (int t = 0; t < T; ++t)
+            if (tileN[t] == N) tl.push_back(t);
+        if (tl.empty()) continue;
+        LvPlan L{};
+        L.N = N;
+        auto add_items = [&](const std::vector<int> &ts, int64_t &off, int64_t &cnt) {
+            std::vector<std::pair<int64_t, int2>> v;
+            for (int t : ts) {
+                const int P = td[t].P;
+                const int64_t cost = (int64_t)b->si[td[t].job].n / P;
+                for (int p = 0; p < P; ++p) v.push_back({cost, make_int2(t, p)});
+            }
+            std::stable_sort(v.begin(), v.end(),
+                             [](const std::pair<int64_t, int2> &a,
+                                const std::pair<int64_t, int2> &bb) { return a.first > bb.first; });
+            off = (int64_t)items.size();
+            cnt = (int64_t)v.size();
+            for (auto &e : v) items.push_back(e.second);
+        };
+        add_items(tl, L.it_rel, L.n_rel);
+        for (int d = 0; d < NDCLS; ++d) {
+            std::vector<int> td_d;
+            for (int t : tl)
+                if (tileD[t] == d) td_d.push_back(t);
+            add_items(td_d, L.it_ex[d], L.n_ex[d]);
+            L.pld[d] = (int64_t)lists.size();
+            for (int t : td_d)
+                if (td[t].P > 1) lists.push_back(t);
+            L.npld[d] = (int64_t)lists.size() - L.pld[d];
+        }
+        L.pl = (int64_t)lists.size();
+        for (int t : tl)
+            if (td[t].P > 1) lists.push_back(t);
+        L.npl = (int64_t)lists.size() - L.pl;
+        lp.push_back(L);
+    }
+    std::vector<BJob> bj(b->jobs.size());
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        bj[j].ids = b->jobs[j].ids;
+        bj[j].ticks = b->jobs[j].ticks;
+        bj[j].n = (int)b->jobs[j].n;
+        bj[j].theta = b->jobs[j].theta;
+        bj[j].upper = b->jobs[j].upper_out;
+        bj[j].exact = b->jobs[j].exact_out;
+    }
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipStreamSynchronize(s));
+    if ((rc = ensure(c, b->tilesd, std::max<size_t>(td.size(), 1) * sizeof(TileDesc)))) return rc;
+    if ((rc = ensure(c, b->jobsd, std::max<size_t>(bj.size(), 1) * sizeof(BJob)))) return rc;
+    if ((rc = ensure(c, b->itemsd, std::max<size_t>(items.size(), 1) * sizeof(int2)))) return rc;
+    if ((rc = ensure(c, b->listsd, std::max<size_t>(lists.size(), 1) * sizeof(int)))) return rc;
+    if ((rc = ensure(c, b->lamd, std::max<int64_t>(lam_off, 1) * sizeof(int)))) return rc;
+    if ((rc = ensure(c, b->tbld, std::max<int64_t>(tbl_off, 1) * sizeof(int2)))) return rc;
+    if ((rc = ensure(c, b->flagsr, std::max<int64_t>((int64_t)T * WAVE, 1) * sizeof(int)))) return rc;
+    if ((rc = ensure(c, b->flagsx, std::max<int64_t>((int64_t)T * WAVE, 1) * sizeof(int)))) return rc;
+    if ((rc = ensure(c, b->qctr, (size_t)(NMAX * (1 + NDCLS)) * sizeof(int)))) return rc;
+    HIPCHK(c, hipMemcpy(b->tilesd.p, td.data(), td.size() * sizeof(TileDesc), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(b->jobsd.p, bj.data(), bj.size() * sizeof(BJob), hipMemcpyHostToDevice));
+    if (!items.empty())
+        HIPCHK(c, hipMemcpy(b->itemsd.p, items.data(), items.size() * sizeof(int2),
+                            hipMemcpyHostToDevice));
+    if (!lists.empty())
+        HIPCHK(c, hipMemcpy(b->listsd.p, lists.data(), lists.size() * sizeof(int),
+                            hipMemcpyHostToDevice));
+    launch_fill(P<int>(b->flagsr), 0, (int64_t)T * WAVE, s);
+    launch_fill(P<int>(b->flagsx), 0, (int64_t)T * WAVE, s);
+    HIPCHK(c, hipStreamSynchronize(s));
+
+    const int grid = std::max(1, b->ncu * b->tun.waves_per_cu / WPB);
+    int *lists_d = P<int>(b->listsd);
+    int q = 0;
+    for (const LvPlan &L : lp) {
+        fe_batch::Level lv;
+        lv.N = L.N;
+        HIPCHK(c, hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+        hipStream_t cs = b->cap;
+        BatchDev d;
+        d.tiles = (const TileDesc *)b->tilesd.p;
+        d.jobs = (const BJob *)b->jobsd.p;
+        d.pk = P<int>(b->pk);
+        d.orig = P<int>(b->origd);
+        d.lam = P<int>(b->lamd);
+        d.tbl = P<int2>(b->tbld);
+        d.status = P<int>(c->status);
+        const int q0 = q;
+        int nq = 1;
+        for (int dd = 0; dd < NDCLS; ++dd) nq += L.n_ex[dd] > 0;
+        launch_fill(P<int>(b->qctr) + q0, 0, nq, cs);
+        launch_clear_flags(lists_d + L.pl, (int)L.npl, P<int>(b->flagsr), P<int>(b->flagsx), cs);
+        launch_plan_batch(d.tiles, d.jobs, P<int>(b->tileWd), lists_d + L.pl, (int)L.npl,
+                          P<int>(b->lamd), cs);
+        // pass 1: relaxed, every candidate of this size
+        d.items = P<int2>(b->itemsd) + L.it_rel;
+        d.nitems = (int)L.n_rel;
+        d.qctr = P<int>(b->qctr) + q++;
+        d.flags = P<int>(b->flagsr);
+        launch_persist(L.N, false, 0, d, grid, cs);
+        launch_concat_batch(d, lists_d + L.pl, (int)L.npl, false, cs);
+        launch_persist_fixup(L.N, false, 0, d, lists_d + L.pl, (int)L.npl, cs);
+        // pass 2: exact, survivors only
+        d.flags = P<int>(b->flagsx);
+        for (int dd = 0; dd < NDCLS; ++dd) {
+            if (!L.n_ex[dd]) continue;
+            d.items = P<int2>(b->itemsd) + L.it_ex[dd];
+            d.nitems = (int)L.n_ex[dd];
+            d.qctr = P<int>(b->qctr) + q++;
+            launch_persist(L.N, true, dd, d, grid, cs);
+        }
+        launch_concat_batch(d, lists_d + L.pl, (int)L.npl, true, cs);
+        for (int dd = 0; dd < NDCLS; ++dd)
+            if (L.npld[dd])
+                launch_persist_fixup(L.N, true, dd, d, lists_d + L.pld[dd], (int)L.npld[dd], cs);
+        hipError_t e1 = hipStreamEndCapture(b->cap, &lv.g);
+        if (e1 != hipSuccess) return fail(c, FE_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1));
+        HIPCHK(c, hipGraphInstantiate(&lv.x, lv.g, nullptr, nullptr, 0));
+        b->levels.push_back(lv);
+        (void)q0;
+    }
+    return FE_OK;
+}
+
+}  // namespace
+
+extern "C" int fe_batch_create(fe_ctx *c, int32_t R, const fe_job *jobs, fe_batch **out)
+{
+    int rc;
+    if (!c || !out) return FE_EINVAL;
+    *out = nullptr;
+    if (R < 0 || (R > 0 && !jobs)) return fail(c, FE_EINVAL, "bad job list");
+    for (int r = 0; r < R; ++r) {
+        const fe_job &j = jobs[r];
+        if ((rc = check_common(c, j.ids, j.ticks, j.n, j.num_types))) return rc;
+        if ((rc = check_cands(c, j.types, j.len, j.lo, j.hi, j.M, j.nmax))) return rc;
+        if (j.M > 0 && (!j.upper_out || !j.exact_out))
+            return fail(c, FE_EINVAL, "job %d: null output", r);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    fe_batch *b = new (std::nothrow) fe_batch();
+    if (!b) return fail(c, FE_ENOMEM, "host allocation failed");
+    b->c = c;
+    b->jobs.assign(jobs, jobs + R);
+    b->si.resize(R);
+    (void)hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return fail(c, FE_EDEVICE, "stream creation failed");
+    }
+    auto bail = [&](int code) {
+        fe_batch_destroy(b);
+        return code;
+    };
+    // validate the streams and learn their spans
+    for (int r = 0; r < R; ++r)
+        if ((rc = stream_info(c, jobs[r].ids, jobs[r].ticks, (int)jobs[r].n, jobs[r].num_types,
+                              b->si[r])))
+            return bail(rc);
+    // candidate tables to the host, checked, tiled per episode size
+    int64_t rec_total = 0;
+    for (int r = 0; r < R; ++r) {
+        const fe_job &j = jobs[r];
+        if (j.M == 0) continue;
+        const int nm = j.nmax, hm = std::max(nm - 1, 1);
+        std::vector<int> ty((size_t)j.M * nm), ln(j.M), lo((size_t)j.M * hm), hi((size_t)j.M * hm);
+        HIPCHK(c, hipMemcpy(ty.data(), j.types, ty.size() * sizeof(int), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(ln.data(), j.len, ln.size() * sizeof(int), hipMemcpyDeviceToHost));
+        if (nm > 1) {
+            HIPCHK(c, hipMemcpy(lo.data(), j.lo, (size_t)j.M * (nm - 1) * sizeof(int),
+                                hipMemcpyDeviceToHost));
+            HIPCHK(c, hipMemcpy(hi.data(), j.hi, (size_t)j.M * (nm - 1) * sizeof(int),
+                                hipMemcpyDeviceToHost));
+        }
+        for (int N = 1; N <= nm; ++N) {
+            Episodes C;
+            C.m = N;
+            std::vector<int> back;
+            for (int m = 0; m < j.M; ++m) {
+                const int L = ln[m];
+                if (L < 1 || L > nm) return bail(fail(c, FE_EINVAL, "job %d: bad len", r));
+                if (L != N) continue;
+                int64_t W = 0;
+                for (int k = 0; k < N; ++k) {
+                    const int t = ty[(size_t)m * nm + k];
+                    if (t < 0 || t >= j.num_types)
+                        return bail(fail(c, FE_EINVAL, "job %d: type out of range", r));
+                    C.key.push_back(t);
+                    if (k < N - 1) {
+                        const int l = lo[(size_t)m * (nm - 1) + k], h = hi[(size_t)m * (nm - 1) + k];
+                        if (l < 0 || l >= h || h >= TICK_LIMIT || h / (h - l + 1) >= 8)
+                            return bail(fail(c, FE_EINVAL, "job %d: bad interval", r));
+                        W += h;
+                        C.key.push_back(l);
+                        C.key.push_back(h);
+                    }
+                }
+                if (W >= TICK_LIMIT) return bail(fail(c, FE_EINVAL, "job %d: W too large", r));
+                back.push_back(m);
+            }
+            if (back.empty()) continue;
+            std::vector<int> order(back.size());
+            for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+            HostPack hp;
+            host_pack(C, order, true, hp);
+            for (const GroupDesc &gd : hp.groups) {
+                fe_batch::Group g{r, gd.key, b->ntiles + gd.tile_base, gd.tiles, gd.wmax};
+                b->groups.push_back(g);
+            }
+            b->rec.insert(b->rec.end(), hp.rec.begin(), hp.rec.end());
+            for (int o : hp.orig) b->orig.push_back(o < 0 ? -1 : back[o]);
+            b->tileW.insert(b->tileW.end(), hp.tileW.begin(), hp.tileW.end());
+            b->ntiles += hp.tiles;
+            rec_total += (int64_t)hp.rec.size();
+        }
+    }
+    if ((rc = ensure(c, b->pk, std::max<int64_t>(rec_total, 1) * sizeof(int)))) return bail(rc);
+    if ((rc = ensure(c, b->origd, std::max<size_t>(b->orig.size(), 1) * sizeof(int)))) return bail(rc);
+    if ((rc = ensure(c, b->tileWd, std::max<size_t>(b->tileW.size(), 1) * sizeof(int)))) return bail(rc);
+    if (!b->rec.empty())
+        HIPCHK(c, hipMemcpy(b->pk.p, b->rec.data(), b->rec.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!b->orig.empty())
+        HIPCHK(c, hipMemcpy(b->origd.p, b->orig.data(), b->orig.size() * sizeof(int),
+                            hipMemcpyHostToDevice));
+    if (!b->tileW.empty())
+        HIPCHK(c, hipMemcpy(b->tileWd.p, b->tileW.data(), b->tileW.size() * sizeof(int),
+                            hipMemcpyHostToDevice));
+    b->rec.clear();
+    b->rec.shrink_to_fit();
+    if ((rc = batch_plan(b))) return bail(rc);
+    *out = b;
+    return FE_OK;
+}
+
+extern "C" int fe_batch_run(fe_batch *b)
+{
+    if (!b) return FE_EINVAL;
+    fe_ctx *c = b->c;
+    HIPCHK(c, hipSetDevice(c->device));
+    for (auto &L : b->levels) HIPCHK(c, hipGraphLaunch(L.x, c->stream));
+    return FE_OK;
+}
+
+extern "C" int fe_batch_set_tuning(fe_batch *b, const fe_batch_tuning *t)
+{
+    if (!b || !t || t->seg_events < 256 || t->waves_per_cu < 1 || t->waves_per_cu > 64)
+        return FE_EINVAL;
+    b->tun.seg_events = t->seg_events;
+    b->tun.waves_per_cu = t->waves_per_cu;
+    return batch_plan(b);
+}
+
+extern "C" int fe_batch_get_tuning(const fe_batch *b, fe_batch_tuning *t)
+{
+    if (!b || !t) return FE_EINVAL;
+    *t = b->tun;
+    return FE_OK;
+}
+
+extern "C" int fe_batch_autotune(fe_batch *b, int32_t reps, fe_batch_tuning *best)
+{
+    if (!b || reps < 1) return FE_EINVAL;
+    fe_ctx *c = b->c;
+    int rc;
+    const int segs[] = {8192, 16384, 32768, 65536, 131072};
+    const int wpcs[] = {8, 16, 32};
+    fe_batch_tuning top{0, 0, 1e30};
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    for (int sg : segs)
+        for (int wp : wpcs) {
+            b->tun.seg_events = sg;
+            b->tun.waves_per_cu = wp;
+            if ((rc = batch_plan(b))) return rc;
+            if ((rc = fe_batch_run(b))) return rc;  // warm-up
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            for (int r = 0; r < reps; ++r)
+                if ((rc = fe_batch_run(b))) return rc;
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            if (ms / reps < top.run_ms) top = fe_batch_tuning{sg, wp, ms / reps};
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->tun = top;
+    if ((rc = batch_plan(b))) return rc;
+    if (best) *best = top;
+    return FE_OK;
+}
+
+extern "C" int fe_batch_destroy(fe_batch *b)
+{
+    if (!b) return FE_EINVAL;
+    fe_ctx *c = b->c;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    batch_free_graphs(b);
+    Buf *bufs[] = {&b->pk,    &b->origd, &b->tileWd, &b->tilesd, &b->jobsd,  &b->itemsd,
+                   &b->listsd, &b->lamd, &b->tbld,   &b->flagsr, &b->flagsx, &b->qctr};
+    for (Buf *x : bufs)
+        if (x->p) (void)hipFree(x->p);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return FE_OK;
+}
+
+extern "C" int fe_count_batched(fe_ctx *c, int32_t R, const fe_job *jobs)
+{
+    fe_batch *b = nullptr;
+    int rc = fe_batch_create(c, R, jobs, &b);
+    if (rc) return rc;
+    rc = fe_batch_run(b);
+    if (!rc) rc = fe_sync(c);
+    fe_batch_destroy(b);
+    return rc;
+}

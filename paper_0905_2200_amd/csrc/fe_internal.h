@@ -46,6 +46,38 @@ struct MapGroup {
     int P;
 };
 
+// Batched counting (many recordings): one descriptor per recording and per
+// packed tile, and the arguments of the persistent launches.
+struct BJob {
+    const int *ids, *ticks;
+    int n;
+    int theta;
+    int *upper;  // relaxed counts [M_job]
+    int *exact;  // exact counts [M_job], -1 for pruned
+};
+
+struct TileDesc {
+    int job;      // recording
+    int P;        // segments of the tile's group
+    int64_t rec;  // int offset of the tile record in pk
+    int64_t tbl;  // int2 offset of the tile's slot tables [P][64][KMAX]
+    int64_t lam;  // int offset of the tile's lam[P+1]
+};
+
+struct BatchDev {
+    const TileDesc *tiles;
+    const int2 *items;  // (tile, segment) work items, heaviest first
+    int nitems;
+    int *qctr;          // queue head
+    const BJob *jobs;
+    const int *pk;
+    const int *orig;    // [tiles*64] candidate index within its recording
+    int *lam;
+    int2 *tbl;
+    int *flags;
+    int *status;
+};
+
 // launchers (fe_kernels.hip)
 void launch_fill(int *p, int v, int64_t n, hipStream_t s);
 void launch_validate(const int *ids, const int *ticks, int n, int num_types,
@@ -64,6 +96,14 @@ void launch_plan(const int *ticks, int n, const int *tileW, int tiles, int P,
 void launch_map(int N, bool exact, int dcls, const MapGroup &g, hipStream_t s);
 void launch_concat(const MapGroup &g, bool tree, hipStream_t s);
 void launch_fixup(int N, bool exact, int dcls, const MapGroup &g, hipStream_t s);
+void launch_persist(int N, bool exact, int dcls, const BatchDev &b, int grid, hipStream_t s);
+void launch_persist_fixup(int N, bool exact, int dcls, const BatchDev &b, const int *ctiles,
+                          int nct, hipStream_t s);
+void launch_plan_batch(const TileDesc *tiles, const BJob *jobs, const int *tileW,
+                       const int *ptiles, int npt, int *lam, hipStream_t s);
+void launch_clear_flags(const int *ptiles, int npt, int *fa, int *fb, hipStream_t s);
+void launch_concat_batch(const BatchDev &b, const int *ctiles, int nct, bool exact,
+                         hipStream_t s);
 void launch_compact(const int *vals, int M, int theta, int *pruned_out,
                     int *sel, int *nsel, hipStream_t s);
 void launch_select(const int *vals, const int *src, int M, int theta, int *out, hipStream_t s);

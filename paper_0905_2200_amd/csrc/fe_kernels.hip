@@ -244,6 +244,139 @@ static void dispatch(int N, bool exact, int dcls, const MapGroup &g, hipStream_t
     }
 }
 
+void launch_persist_n1(bool, int, const BatchDev &, int, const int *, int, hipStream_t, bool);
+void launch_persist_n2(bool, int, const BatchDev &, int, const int *, int, hipStream_t, bool);
+void launch_persist_n3(bool, int, const BatchDev &, int, const int *, int, hipStream_t, bool);
+void launch_persist_n4(bool, int, const BatchDev &, int, const int *, int, hipStream_t, bool);
+void launch_persist_n5(bool, int, const BatchDev &, int, const int *, int, hipStream_t, bool);
+void launch_persist_n6(bool, int, const BatchDev &, int, const int *, int, hipStream_t, bool);
+void launch_persist_n7(bool, int, const BatchDev &, int, const int *, int, hipStream_t, bool);
+void launch_persist_n8(bool, int, const BatchDev &, int, const int *, int, hipStream_t, bool);
+
+static void pdispatch(int N, bool exact, int dcls, const BatchDev &b, int grid, const int *ct,
+                      int nct, hipStream_t s, bool fix)
+{
+    switch (N) {
+    case 1: return launch_persist_n1(exact, dcls, b, grid, ct, nct, s, fix);
+    case 2: return launch_persist_n2(exact, dcls, b, grid, ct, nct, s, fix);
+    case 3: return launch_persist_n3(exact, dcls, b, grid, ct, nct, s, fix);
+    case 4: return launch_persist_n4(exact, dcls, b, grid, ct, nct, s, fix);
+    case 5: return launch_persist_n5(exact, dcls, b, grid, ct, nct, s, fix);
+    case 6: return launch_persist_n6(exact, dcls, b, grid, ct, nct, s, fix);
+    case 7: return launch_persist_n7(exact, dcls, b, grid, ct, nct, s, fix);
+    default: return launch_persist_n8(exact, dcls, b, grid, ct, nct, s, fix);
+    }
+}
+
+void launch_persist(int N, bool exact, int dcls, const BatchDev &b, int grid, hipStream_t s)
+{
+    pdispatch(N, exact, dcls, b, grid, nullptr, 0, s, false);
+}
+
+void launch_persist_fixup(int N, bool exact, int dcls, const BatchDev &b, const int *ctiles,
+                          int nct, hipStream_t s)
+{
+    pdispatch(N, exact, dcls, b, 0, ctiles, nct, s, true);
+}
+
+// Look-back starts of every segmented tile of a batch: one wave per tile.
+__global__ void k_plan_batch(const TileDesc *tiles, const BJob *jobs, const int *tileW,
+                             const int *ptiles, int npt, int *lam)
+{
+    const int lane = __lane_id();
+    const int w = uniform_u(blockIdx.x * WPB + (threadIdx.x >> 6));
+    if (w >= npt) return;
+    const int tile = ptiles[w];
+    const TileDesc td = tiles[tile];
+    const BJob jb = jobs[td.job];
+    const int n = jb.n, P = td.P, W = tileW[tile];
+    for (int p = lane; p <= P; p += WAVE) {
+        int v;
+        if (p == 0) {
+            v = 0;
+        } else if (p == P) {
+            v = n;
+        } else {
+            const int L = (int)((int64_t)p * n / P);
+            const int x = jb.ticks[L] - W;
+            int a = 0, b = L;
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (jb.ticks[mid] < x) a = mid + 1;
+                else b = mid;
+            }
+            v = a;
+        }
+        lam[td.lam + p] = v;
+    }
+}
+
+void launch_plan_batch(const TileDesc *tiles, const BJob *jobs, const int *tileW,
+                       const int *ptiles, int npt, int *lam, hipStream_t s)
+{
+    if (npt <= 0) return;
+    hipLaunchKernelGGL(k_plan_batch, dim3((npt + WPB - 1) / WPB), dim3(WAVE * WPB), 0, s, tiles,
+                       jobs, tileW, ptiles, npt, lam);
+}
+
+// Clear the slot-overflow flags of the listed tiles (both passes).
+__global__ void k_clear_flags(const int *ptiles, int npt, int *fa, int *fb)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = g / WAVE, lane = g % WAVE;
+    if (w >= npt) return;
+    const int64_t c = (int64_t)ptiles[w] * WAVE + lane;
+    fa[c] = 0;
+    fb[c] = 0;
+}
+
+void launch_clear_flags(const int *ptiles, int npt, int *fa, int *fb, hipStream_t s)
+{
+    if (npt <= 0) return;
+    const int64_t thr = (int64_t)npt * WAVE;
+    hipLaunchKernelGGL(k_clear_flags, dim3((unsigned)((thr + 255) / 256)), dim3(256), 0, s, ptiles,
+                       npt, fa, fb);
+}
+
+__device__ __forceinline__ int clampk_b(int x) { return x < 0 ? 0 : (x >= KMAX ? KMAX - 1 : x); }
+
+// Concatenate for every segmented tile of a batch: one lane per candidate
+// walks its segments' slot tables.  Exact pass: pruned candidates get -1.
+__global__ void k_concat_batch(BatchDev b, const int *ctiles, int nct, int exact)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = g / WAVE, lane = g % WAVE;
+    if (w >= nct) return;
+    const int tile = ctiles[w];
+    const TileDesc td = b.tiles[tile];
+    const BJob jb = b.jobs[td.job];
+    const int c = tile * WAVE + lane;
+    const int o = b.orig[c];
+    if (o < 0) return;
+    int *out = exact ? jb.exact : jb.upper;
+    if (exact && jb.upper[o] < jb.theta) {
+        out[o] = -1;
+        return;
+    }
+    if (b.flags[c]) return;
+    const int2 *t = b.tbl + td.tbl;
+    int x = 0, tot = 0;
+    for (int p = 0; p < td.P; ++p) {
+        const int2 v = t[((int64_t)p * WAVE + lane) * KMAX + x];
+        tot += v.x;
+        x = clampk_b(v.y);
+    }
+    out[o] = tot;
+}
+
+void launch_concat_batch(const BatchDev &b, const int *ctiles, int nct, bool exact, hipStream_t s)
+{
+    if (nct <= 0) return;
+    const int64_t thr = (int64_t)nct * WAVE;
+    hipLaunchKernelGGL(k_concat_batch, dim3((unsigned)((thr + 255) / 256)), dim3(256), 0, s, b,
+                       ctiles, nct, exact ? 1 : 0);
+}
+
 void launch_map(int N, bool exact, int dcls, const MapGroup &g, hipStream_t s)
 {
     dispatch(N, exact, dcls, g, s, false);

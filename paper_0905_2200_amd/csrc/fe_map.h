@@ -235,14 +235,15 @@ template <int N, bool EXACT, int D> struct MainRun {
     int nx = 0;     // E_(N) events seen at index >= lamn (exit numbering)
     int ks = 0;     // E_(N) events in the look-back [lam, L)
     int q = 0;      // completions seen; the first QREC are kept for merging
-    int ci[QREC], ck[QREC];
+    int ci[QREC], ck[QREC], ct[QREC];  // index, count after it, tick
 
-    __device__ __forceinline__ void note(int idx)
+    __device__ __forceinline__ void note(int idx, int t)
     {
 #pragma unroll
         for (int k = 0; k < QREC; ++k) {
             ci[k] = q == k ? idx : ci[k];
             ck[k] = q == k ? cnt : ck[k];
+            ct[k] = q == k ? t : ct[k];
         }
         ++q;
     }
@@ -262,7 +263,7 @@ template <int N, bool EXACT, int D> struct MainRun {
                 m.reset();
                 ++cnt;
                 lastx = 0;
-                if constexpr (NOTE) note(idx);
+                if constexpr (NOTE) note(idx, t);
             }
         });
     }
@@ -281,7 +282,7 @@ template <int N, bool EXACT, int D> struct MainRun {
                 m.reset();
                 cnt += idx >= L ? 1 : 0;
                 lastx = nx_on ? nx + 1 : 0;
-                note(idx);
+                note(idx, t);
             }
             const bool isN = ev == c.ty[N - 1];
             nx += (nx_on & isN) ? 1 : 0;
@@ -291,8 +292,18 @@ template <int N, bool EXACT, int D> struct MainRun {
 };
 
 // Slot j >= 1: a fresh machine started right after the j-th E_(N) event of
-// the look-back; stops once a completion coincides with one of the slot-0
-// machine's remembered completions.
+// the look-back.  It stops as soon as it is known to behave like the slot-0
+// machine from then on, and takes the rest of the result from that machine:
+//  * at a completion shared with a remembered slot-0 completion (both are
+//    empty afterwards), or
+//  * at the first event more than W ticks after the later of the two
+//    machines' last reset points (their last completion, or the slot's
+//    start): every list entry in which they can differ came from a chain
+//    that began at or before that reset and would need more than W ticks to
+//    reach the event, so both make the same decisions from there on.  This
+//    needs every slot-0 completion before the event to be remembered, and
+//    the event to lie before the next segment's look-back, so that the exit
+//    slot is decided by later (shared) completions only.
 template <int N, bool EXACT, int D>
 __device__ void slot_pass(cptr ids, cptr ticks, int lam, int L, int R, int lamn, int j,
                           bool act, const Cand<N> &c, const MainRun<N, EXACT, D> &mr,
@@ -301,10 +312,35 @@ __device__ void slot_pass(cptr ids, cptr ticks, int lam, int L, int R, int lamn,
     constexpr int U = Unroll<N, EXACT, D>::U;
     typename MachineOf<N, EXACT, D>::type m;
     m.reset();
+    int W = 0;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) W += c.hi[k];
     int cnt = 0, lastx = 0, nx = 0, seen = 0;
+    int rt = 0;  // tick of this machine's last reset point
     bool started = false, live = act;
     int i = uniform(lam);
     const int e = uniform(R);
+    auto take_rest = [&](int ckk) {
+        cnt += mr.cnt - ckk;
+        lastx = mr.lastx;
+        live = false;
+    };
+    // horizon test before processing event idx (tick t)
+    auto horizon = [&](int idx, int t) {
+        if (!(live & started) || idx > lamn) return;
+        int kk = -1;
+#pragma unroll
+        for (int k = 0; k < QREC; ++k) kk = (k < mr.q && mr.ci[k] < idx) ? k : kk;
+        const bool known = mr.q <= QREC || mr.ci[QREC - 1] >= idx;
+        int mt = rt, ckk = 0;
+#pragma unroll
+        for (int k = 0; k < QREC; ++k)
+            if (k == kk) {
+                mt = mr.ct[k] > rt ? mr.ct[k] : rt;
+                ckk = mr.ck[k];
+            }
+        if (known && t > mt + W) take_rest(ckk);
+    };
     auto f = [&](int ev, int t, int idx) {
         const bool isN = ev == c.ty[N - 1];
         const bool nx_on = idx >= lamn;
@@ -313,6 +349,7 @@ __device__ void slot_pass(cptr ids, cptr ticks, int lam, int L, int R, int lamn,
             m.reset();
             cnt += idx >= L ? 1 : 0;
             lastx = nx_on ? nx + 1 : 0;
+            rt = t;
             // merge with the slot-0 machine at a shared completion
             int hitk = -1;
 #pragma unroll
@@ -321,15 +358,14 @@ __device__ void slot_pass(cptr ids, cptr ticks, int lam, int L, int R, int lamn,
                 int ckk = 0;
 #pragma unroll
                 for (int k = 0; k < QREC; ++k) ckk = k == hitk ? mr.ck[k] : ckk;
-                cnt += mr.cnt - ckk;
-                lastx = mr.lastx;
-                live = false;
+                take_rest(ckk);
             }
         }
         const bool starts = live & !started & isN & (idx < L) & (seen + 1 == j);
         if (starts) {
             started = true;
             lastx = nx_on ? nx + 1 : 0;
+            rt = t;
         }
         seen += (isN & (idx < L)) ? 1 : 0;
         nx += (isN & nx_on) ? 1 : 0;
@@ -339,12 +375,15 @@ __device__ void slot_pass(cptr ids, cptr ticks, int lam, int L, int R, int lamn,
         int ev[U], tv[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) { ev[k] = ids[i + k]; tv[k] = ticks[i + k]; }
+        horizon(i, tv[0]);
 #pragma unroll
         for (int k = 0; k < U; ++k) f(ev[k], tv[k], i + k);
     }
     for (; i < e; ++i) {
         if (__ballot(live) == 0) break;
-        f(ids[i], ticks[i], i);
+        const int t = ticks[i];
+        horizon(i, t);
+        f(ids[i], t, i);
     }
     out_cnt = cnt;
     out_x = lastx;
@@ -372,55 +411,60 @@ __device__ __forceinline__ bool shared_prefix(const Cand<N> &c, bool valid, Pref
     }
 }
 
-template <int N, bool EXACT, int D>
-__global__ __launch_bounds__(WAVE *WPB) void k_map(const int *__restrict__ ids_,
-                                                   const int *__restrict__ ticks_, MapGroup g)
-{
-    cptr ids = (cptr)ids_;
-    cptr ticks = (cptr)ticks_;
-    const int lane = __lane_id();
-    const int w = uniform(blockIdx.x * WPB + (threadIdx.x >> 6));
-    const int P = g.P, tiles = g.tiles;
-    if (w >= tiles * P) return;
-    const int p = w / tiles, tile = w - p * tiles;
-    const int c = tile * WAVE + lane;
-    const int o = g.orig[c];
+// Everything one work item (a tile of 64 candidates over segment p of P)
+// needs; shared by the per-group launch (k_map) and the persistent batched
+// launch (k_persist).
+struct ItemArgs {
+    cptr ids, ticks;
+    int n;
+    const int *rec;  // the tile's packed record
+    int P, p;
+    const int *lam;  // the tile's look-back starts lam[0..P] (P > 1)
+    int2 *tb;        // this lane's KMAX slot entries for segment p (P > 1)
+    int *flag;       // this lane's slot-overflow flag (P > 1)
+    int *out;        // counts, indexed by the candidate's input index
+    int *status;
+};
 
+// Map step of one work item.  o: the lane's candidate index (-1 = padding);
+// valid: the lane's candidate takes part (its result is written).
+template <int N, bool EXACT, int D>
+__device__ __forceinline__ void map_item(const ItemArgs &a, int o, bool valid)
+{
     Cand<N> cd;
-    load_cand<N>(cd, g.pk + (int64_t)tile * rec_ints(N), lane);
+    load_cand<N>(cd, a.rec, __lane_id());
     Prefix<N> u;
-    const bool uni = shared_prefix<N>(cd, o >= 0, u);
+    const bool uni = shared_prefix<N>(cd, valid, u);
 
     MainRun<N, EXACT, D> r;
     r.m.reset();
-    if (P == 1) {
-        if (uni) r.template body<true, false>(ids, ticks, 0, g.n, cd, u, g.status);
-        else r.template body<false, false>(ids, ticks, 0, g.n, cd, u, g.status);
-        if (o >= 0) g.out[o] = r.cnt;
+    if (a.P == 1) {
+        if (uni) r.template body<true, false>(a.ids, a.ticks, 0, a.n, cd, u, a.status);
+        else r.template body<false, false>(a.ids, a.ticks, 0, a.n, cd, u, a.status);
+        if (valid) a.out[o] = r.cnt;
         return;
     }
 
-    const int n = g.n;
+    const int n = a.n, P = a.P, p = a.p;
     const int L = (int)((int64_t)p * n / P);
     const int R = (int)((int64_t)(p + 1) * n / P);
-    const int lam = uniform(g.lam[(int64_t)tile * (P + 1) + p]);
-    const int lamn = uniform(g.lam[(int64_t)tile * (P + 1) + p + 1]);
+    const int lam = uniform(a.lam[p]);
+    const int lamn = uniform(a.lam[p + 1]);
     const int x = lamn < lam ? lam : (lamn > R ? R : lamn);
     const int xl = x > L ? x : L;
-    int2 *tb = g.tbl + ((int64_t)p * tiles * WAVE + c) * KMAX;
 
     // slot 0: the last completion before L lies before lam
-    for (int k = 0; k < QREC; ++k) { r.ci[k] = -1; r.ck[k] = 0; }
-    r.edge(ids, ticks, lam, L, L, lamn, cd, g.status);
-    if (uni) r.template body<true, true>(ids, ticks, L, xl, cd, u, g.status);
-    else r.template body<false, true>(ids, ticks, L, xl, cd, u, g.status);
-    r.edge(ids, ticks, xl, R, L, lamn, cd, g.status);
-    tb[0] = make_int2(r.cnt, r.lastx < KMAX ? r.lastx : KMAX - 1);
+    for (int k = 0; k < QREC; ++k) { r.ci[k] = -1; r.ck[k] = 0; r.ct[k] = 0; }
+    r.edge(a.ids, a.ticks, lam, L, L, lamn, cd, a.status);
+    if (uni) r.template body<true, true>(a.ids, a.ticks, L, xl, cd, u, a.status);
+    else r.template body<false, true>(a.ids, a.ticks, L, xl, cd, u, a.status);
+    r.edge(a.ids, a.ticks, xl, R, L, lamn, cd, a.status);
+    if (valid) a.tb[0] = make_int2(r.cnt, r.lastx < KMAX ? r.lastx : KMAX - 1);
 
     const int K = r.ks + 1;  // slots of this lane
     const bool ovf = K > KMAX;
-    if (ovf && o >= 0) g.flags[c] = 1;
-    int kw = (ovf || o < 0) ? 1 : K;
+    if (ovf && valid) *a.flag = 1;
+    int kw = (ovf || !valid) ? 1 : K;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         const int ok = __shfl_xor(kw, off);
@@ -428,10 +472,77 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map(const int *__restrict__ ids_,
     }
     kw = uniform(kw);
     for (int j = 1; j < kw; ++j) {
-        const bool act = !ovf && o >= 0 && j < K;
+        const bool act = !ovf && valid && j < K;
         int sc = 0, sx = 0;
-        slot_pass<N, EXACT, D>(ids, ticks, lam, L, R, lamn, j, act, cd, r, g.status, sc, sx);
-        if (act) tb[j] = make_int2(sc, sx < KMAX ? sx : KMAX - 1);
+        slot_pass<N, EXACT, D>(a.ids, a.ticks, lam, L, R, lamn, j, act, cd, r, a.status, sc, sx);
+        if (act) a.tb[j] = make_int2(sc, sx < KMAX ? sx : KMAX - 1);
+    }
+}
+
+template <int N, bool EXACT, int D>
+__global__ __launch_bounds__(WAVE *WPB) void k_map(const int *__restrict__ ids_,
+                                                   const int *__restrict__ ticks_, MapGroup g)
+{
+    const int lane = __lane_id();
+    const int w = uniform(blockIdx.x * WPB + (threadIdx.x >> 6));
+    const int P = g.P, tiles = g.tiles;
+    if (w >= tiles * P) return;
+    const int p = w / tiles, tile = w - p * tiles;
+    const int c = tile * WAVE + lane;
+    const int o = g.orig[c];
+    ItemArgs a;
+    a.ids = (cptr)ids_;
+    a.ticks = (cptr)ticks_;
+    a.n = g.n;
+    a.rec = g.pk + (int64_t)tile * rec_ints(N);
+    a.P = P;
+    a.p = p;
+    a.lam = P > 1 ? g.lam + (int64_t)tile * (P + 1) : nullptr;
+    a.tb = P > 1 ? g.tbl + ((int64_t)p * tiles * WAVE + c) * KMAX : nullptr;
+    a.flag = P > 1 ? g.flags + c : nullptr;
+    a.out = g.out;
+    a.status = g.status;
+    map_item<N, EXACT, D>(a, o, o >= 0);
+}
+
+// Persistent batched Map: a grid sized to the machine pops (tile, segment)
+// items of many recordings from a queue (heaviest first) until it is empty.
+// In the exact pass only candidates that survived the relaxed pass count;
+// the others get -1.
+template <int N, bool EXACT, int D>
+__global__ __launch_bounds__(WAVE *WPB) void k_persist(BatchDev b)
+{
+    const int lane = __lane_id();
+    for (;;) {
+        int it = 0;
+        if (lane == 0) it = atomicAdd(b.qctr, 1);
+        it = uniform(__shfl(it, 0));
+        if (it >= b.nitems) break;
+        const int2 tp = b.items[it];
+        const int tile = uniform(tp.x), p = uniform(tp.y);
+        const TileDesc td = b.tiles[tile];
+        const BJob jb = b.jobs[uniform(td.job)];
+        const int c = tile * WAVE + lane;
+        const int o = b.orig[c];
+        int *out = EXACT ? jb.exact : jb.upper;
+        bool valid = o >= 0;
+        if (EXACT) valid = valid && jb.upper[o] >= jb.theta;
+        const int P = uniform(td.P);
+        if (EXACT && P == 1 && o >= 0 && !valid) out[o] = -1;
+        if (__ballot(valid) == 0) continue;
+        ItemArgs a;
+        a.ids = (cptr)jb.ids;
+        a.ticks = (cptr)jb.ticks;
+        a.n = jb.n;
+        a.rec = b.pk + td.rec;
+        a.P = P;
+        a.p = p;
+        a.lam = b.lam + td.lam;
+        a.tb = b.tbl + td.tbl + ((int64_t)p * WAVE + lane) * KMAX;
+        a.flag = b.flags + c;
+        a.out = out;
+        a.status = b.status;
+        map_item<N, EXACT, D>(a, o, valid);
     }
 }
 
@@ -462,6 +573,62 @@ __global__ __launch_bounds__(WAVE *WPB) void k_fixup(const int *__restrict__ ids
         }
     });
     if (f) g.out[o] = cnt;
+}
+
+// Batched recount of flagged candidates: one wave per listed tile.
+template <int N, bool EXACT, int D>
+__global__ __launch_bounds__(WAVE *WPB) void k_persist_fixup(BatchDev b, const int *ctiles,
+                                                             int nct)
+{
+    const int lane = __lane_id();
+    const int w = uniform(blockIdx.x * WPB + (threadIdx.x >> 6));
+    if (w >= nct) return;
+    const int tile = uniform(ctiles[w]);
+    const TileDesc td = b.tiles[tile];
+    const BJob jb = b.jobs[uniform(td.job)];
+    const int c = tile * WAVE + lane;
+    const int o = b.orig[c];
+    bool f = o >= 0 && b.flags[c] != 0;
+    if (EXACT) f = f && jb.upper[o] >= jb.theta;
+    if (__ballot(f) == 0) return;
+    Cand<N> cd;
+    load_cand<N>(cd, b.pk + td.rec, lane);
+    typename MachineOf<N, EXACT, D>::type m;
+    m.reset();
+    int cnt = 0;
+    for_events<Unroll<N, EXACT, D>::U>((cptr)jb.ids, (cptr)jb.ticks, 0, jb.n,
+                                       [&](int ev, int t, int) {
+                                           if (m.step(ev, t, cd, f, b.status)) {
+                                               m.reset();
+                                               ++cnt;
+                                           }
+                                       });
+    if (f) (EXACT ? jb.exact : jb.upper)[o] = cnt;
+}
+
+template <int N, bool EXACT, int D>
+void persist_n(const BatchDev &b, int grid, const int *ctiles, int nct, hipStream_t s, bool fix)
+{
+    if (fix) {
+        if (nct > 0)
+            hipLaunchKernelGGL((k_persist_fixup<N, EXACT, D>), dim3((nct + WPB - 1) / WPB),
+                               dim3(WAVE * WPB), 0, s, b, ctiles, nct);
+    } else {
+        hipLaunchKernelGGL((k_persist<N, EXACT, D>), dim3(grid), dim3(WAVE * WPB), 0, s, b);
+    }
+}
+
+template <int N>
+void persist_dispatch_n(bool exact, int dcls, const BatchDev &b, int grid, const int *ctiles,
+                        int nct, hipStream_t s, bool fix)
+{
+    if (!exact) return persist_n<N, false, 1>(b, grid, ctiles, nct, s, fix);
+    switch (dcls) {
+    case 0: return persist_n<N, true, 1>(b, grid, ctiles, nct, s, fix);
+    case 1: return persist_n<N, true, 2>(b, grid, ctiles, nct, s, fix);
+    case 2: return persist_n<N, true, 4>(b, grid, ctiles, nct, s, fix);
+    default: return persist_n<N, true, 8>(b, grid, ctiles, nct, s, fix);
+    }
 }
 
 template <int N, bool EXACT, int D> void map_n(const MapGroup &g, hipStream_t s, bool fix)

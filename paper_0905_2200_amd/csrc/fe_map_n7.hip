@@ -6,4 +6,9 @@ void launch_map_n7(bool exact, int dcls, const MapGroup &g, hipStream_t s, bool 
 {
     map_dispatch_n<7>(exact, dcls, g, s, fix);
 }
+void launch_persist_n7(bool exact, int dcls, const BatchDev &b, int grid, const int *ctiles,
+                       int nct, hipStream_t s, bool fix)
+{
+    persist_dispatch_n<7>(exact, dcls, b, grid, ctiles, nct, s, fix);
+}
 }  // namespace fe

@@ -24,7 +24,9 @@ STATUS_NAMES = {0: "FE_OK", 1: "FE_EINVAL", 2: "FE_ENOMEM", 3: "FE_EDEVICE",
 
 EXPORTS = ["fe_create", "fe_destroy", "fe_last_error", "fe_sync", "fe_set_param",
            "fe_get_param", "fe_validate", "fe_count", "fe_count_two_pass", "fe_mine",
-           "fe_result_free", "fe_get_stats", "fe_get_kernel_stats", "fe_reset_kernel_stats"]
+           "fe_result_free", "fe_get_stats", "fe_get_kernel_stats", "fe_reset_kernel_stats",
+           "fe_batch_create", "fe_batch_run", "fe_batch_autotune", "fe_batch_set_tuning",
+           "fe_batch_get_tuning", "fe_batch_destroy", "fe_count_batched"]
 
 
 class FeError(RuntimeError):
@@ -54,6 +56,19 @@ class _Stats(ctypes.Structure):
 class _KStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("ee", ctypes.c_double)]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("ids", ctypes.c_void_p), ("ticks", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("num_types", ctypes.c_int32), ("types", ctypes.c_void_p),
+                ("len", ctypes.c_void_p), ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p),
+                ("M", ctypes.c_int32), ("nmax", ctypes.c_int32), ("theta", ctypes.c_int32),
+                ("upper_out", ctypes.c_void_p), ("exact_out", ctypes.c_void_p)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("seg_events", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("run_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -87,6 +102,13 @@ def lib():
         "fe_get_kernel_stats": ([CTX, ctypes.POINTER(_KStat), I32, ctypes.POINTER(I32)],
                                 ctypes.c_int),
         "fe_reset_kernel_stats": ([CTX], ctypes.c_int),
+        "fe_batch_create": ([CTX, I32, ctypes.POINTER(_Job), ctypes.POINTER(V)], ctypes.c_int),
+        "fe_batch_run": ([V], ctypes.c_int),
+        "fe_batch_autotune": ([V, I32, ctypes.POINTER(_Tuning)], ctypes.c_int),
+        "fe_batch_set_tuning": ([V, ctypes.POINTER(_Tuning)], ctypes.c_int),
+        "fe_batch_get_tuning": ([V, ctypes.POINTER(_Tuning)], ctypes.c_int),
+        "fe_batch_destroy": ([V], ctypes.c_int),
+        "fe_count_batched": ([CTX, I32, ctypes.POINTER(_Job)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -284,3 +306,59 @@ class Context:
         finally:
             lib().fe_result_free(res)
         return out
+
+
+class Batch:
+    """Two-pass counting of many recordings as one planned batch (one
+    captured graph per episode size, persistent launches).  `recs` is a list
+    of dicts with device tensors: ids, ticks, num_types, cand (from
+    Context.cand_tensors), theta.  Outputs: self.upper[r], self.exact[r]."""
+
+    def __init__(self, ctx, recs):
+        import torch
+        self.ctx = ctx
+        self.recs = recs
+        self.upper, self.exact = [], []
+        jobs = (_Job * max(len(recs), 1))()
+        for r, rec in enumerate(recs):
+            c = rec["cand"]
+            up = torch.empty(max(c["M"], 1), dtype=torch.int32, device=ctx.device)
+            ex = torch.empty(max(c["M"], 1), dtype=torch.int32, device=ctx.device)
+            self.upper.append(up[:c["M"]])
+            self.exact.append(ex[:c["M"]])
+            jobs[r] = _Job(rec["ids"].data_ptr(), rec["ticks"].data_ptr(), rec["ids"].numel(),
+                           int(rec["num_types"]), c["types"].data_ptr(), c["len"].data_ptr(),
+                           c["lo"].data_ptr(), c["hi"].data_ptr(), c["M"], c["nmax"],
+                           int(rec["theta"]), up.data_ptr(), ex.data_ptr())
+        self._jobs = jobs
+        h = ctypes.c_void_p()
+        ctx._check(ctx._call(lib().fe_batch_create, ctx.h, len(recs), jobs, ctypes.byref(h)))
+        self.h = h
+
+    def run(self):
+        self.ctx._check(self.ctx._call(lib().fe_batch_run, self.h))
+
+    def autotune(self, reps=2):
+        t = _Tuning()
+        self.ctx._check(self.ctx._call(lib().fe_batch_autotune, self.h, int(reps), ctypes.byref(t)))
+        return {"seg_events": t.seg_events, "waves_per_cu": t.waves_per_cu, "run_ms": t.run_ms}
+
+    def set_tuning(self, seg_events, waves_per_cu):
+        t = _Tuning(int(seg_events), int(waves_per_cu), 0.0)
+        self.ctx._check(self.ctx._call(lib().fe_batch_set_tuning, self.h, ctypes.byref(t)))
+
+    def tuning(self):
+        t = _Tuning()
+        self.ctx._check(lib().fe_batch_get_tuning(self.h, ctypes.byref(t)))
+        return {"seg_events": t.seg_events, "waves_per_cu": t.waves_per_cu, "run_ms": t.run_ms}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fe_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -159,12 +159,19 @@ def sub_episodes(cascade, length):
 
 def random_episodes(rng, M, n_types, N, interval_set, n_min=None):
     """M random episodes with N nodes (or N drawn from [n_min, N])."""
+    if M <= 0:
+        return []
+    ks = np.full(M, N) if n_min is None else rng.integers(n_min, N + 1, size=M)
+    ty = rng.integers(0, n_types, size=(M, N))
+    iv = rng.integers(0, len(interval_set), size=(M, max(N - 1, 1)))
+    los = np.array([a for a, _ in interval_set])
+    his = np.array([b for _, b in interval_set])
     out = []
-    for _ in range(M):
-        k = N if n_min is None else int(rng.integers(n_min, N + 1))
-        ty = tuple(int(x) for x in rng.integers(0, n_types, size=k))
-        iv = [interval_set[int(rng.integers(len(interval_set)))] for _ in range(k - 1)]
-        out.append((ty, tuple(l for l, _ in iv), tuple(h for _, h in iv)))
+    for m in range(M):
+        k = int(ks[m])
+        out.append((tuple(int(x) for x in ty[m, :k]),
+                    tuple(int(x) for x in los[iv[m, :k - 1]]),
+                    tuple(int(x) for x in his[iv[m, :k - 1]])))
     return out
 
 
