@@ -222,6 +222,83 @@ int fe_batch_destroy(fe_batch *b);
 /* Convenience: create a batch, run it once, synchronise, destroy it. */
 int fe_count_batched(fe_ctx *ctx, int32_t R, const fe_job *jobs);
 
+/* -------------------------------------------------------------- serving */
+
+/* A window-counting service over many device-resident event streams
+ * ("arrays", e.g. one per multi-electrode array) and one resident candidate
+ * set: each request asks for the two-pass count (Algorithm 4) of every
+ * resident candidate over one array's events with ticks in
+ * [t_begin, t_end).  This serves the paper's goal of processing partitions
+ * of a live stream in turn (Sec. 1).  A scheduler thread inside the library
+ * admits waiting requests into rounds while their summed device footprint
+ * fits the per-round share of the HBM budget, and keeps up to max_inflight
+ * rounds on the GPU at once (one stream each): requests that arrive while
+ * others run join the next round as soon as a stream and memory free up. */
+typedef struct fe_server fe_server;
+
+typedef struct fe_server_config {
+    int32_t n_arrays;      /* number of streams                               */
+    int64_t capacity;      /* events each array's device buffer holds          */
+    int64_t hbm_budget;    /* bytes of per-request device state in flight      */
+    int32_t max_inflight;  /* rounds on the device at once (>= 1)              */
+    int32_t max_round;     /* requests per round (>= 1)                        */
+    int32_t seg_events;    /* target events per work item (0: 16384)           */
+    int32_t waves_per_cu;  /* persistent waves per compute unit (0: 16)        */
+} fe_server_config;
+
+typedef struct fe_request {
+    int32_t array;
+    int32_t t_begin, t_end; /* window of ticks [t_begin, t_end)               */
+    int32_t theta;          /* support threshold of this request              */
+    int64_t arrival_ns;     /* caller's steady-clock arrival time; 0 = now    */
+} fe_request;
+
+typedef struct fe_response {
+    int32_t status;         /* FE_OK, or why the request failed               */
+    int32_t n_events;       /* events in the window                           */
+    int32_t n_survivors;    /* candidates kept by the relaxed pass            */
+    int32_t n_frequent;     /* candidates with exact count >= theta           */
+    const int32_t *upper;   /* [M] host, valid until fe_server_release        */
+    const int32_t *exact;   /* [M] host, -1 for pruned candidates             */
+    int64_t arrival_ns, admit_ns, done_ns; /* steady clock (ns)               */
+    int32_t round, round_size;             /* the round it ran in, its size   */
+} fe_response;
+
+typedef struct fe_server_stats {
+    int64_t submitted, completed, rejected, rounds;
+    int32_t largest_round, max_inflight_seen;
+} fe_server_stats;
+
+/* Create a server: the resident candidates (device table, fe_count layout)
+ * are checked and packed once; num_types is a host array [n_arrays]. */
+int fe_server_create(fe_ctx *ctx, const fe_server_config *cfg, const int32_t *num_types,
+                     const int32_t *types, const int32_t *len, const int32_t *lo,
+                     const int32_t *hi, int32_t M, int32_t nmax, fe_server **out);
+
+/* Append n events (host arrays, sorted, not earlier than the array's last
+ * event, ids in range) to an array's device buffer.  FE_ENOMEM when the
+ * buffer would overflow. */
+int fe_server_append(fe_server *s, int32_t array, const int32_t *ids, const int32_t *ticks,
+                     int64_t n);
+
+/* Queue a request; *ticket identifies it. */
+int fe_server_submit(fe_server *s, const fe_request *req, uint64_t *ticket);
+
+/* FE_EBUSY while the request is queued or running; FE_OK with *out filled
+ * once it is done (out->status tells whether it succeeded). */
+int fe_server_poll(fe_server *s, uint64_t ticket, fe_response *out);
+
+/* Block until the request is done, then as fe_server_poll. */
+int fe_server_wait(fe_server *s, uint64_t ticket, fe_response *out);
+
+/* Forget a finished request and free its host results. */
+int fe_server_release(fe_server *s, uint64_t ticket);
+
+int fe_server_get_stats(fe_server *s, fe_server_stats *out);
+
+/* Stop the scheduler (finishing the rounds in flight) and free everything. */
+int fe_server_destroy(fe_server *s);
+
 /* Per-call statistics of the last fe_count / fe_count_two_pass / fe_mine
  * call on this context (host memory owned by ctx). */
 typedef struct fe_stats {

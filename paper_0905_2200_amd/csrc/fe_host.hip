@@ -12,8 +12,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <condition_variable>
+#include <deque>
 #include <map>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <thread>
 #include <vector>
 
@@ -1161,6 +1165,7 @@ int batch_plan(fe_batch *b)
         for (int t = g.t0; t < g.t0 + g.tiles; ++t) {
             td[t].job = g.job;
             td[t].P = P;
+            td[t].otile = t;
             td[t].rec = 0;
             td[t].lam = lam_off;
             td[t].tbl = tbl_off;
@@ -1511,4 +1516,662 @@ extern "C" int fe_count_batched(fe_ctx *c, int32_t R, const fe_job *jobs)
     if (!rc) rc = fe_sync(c);
     fe_batch_destroy(b);
     return rc;
+}
+
+// ====================================================================== serving
+
+namespace {
+
+int64_t steady_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+}  // namespace
+
+struct fe_server {
+    fe_ctx *c = nullptr;
+    fe_server_config cfg{};
+    int M = 0;
+    // resident candidates, packed once
+    Buf pk, origd, tileWd;
+    std::vector<GroupDesc> groups;
+    std::vector<int64_t> tile_rec;  // record offset per packed tile
+    std::vector<int> tile_key;      // group key per packed tile
+    std::vector<int> tile_w;        // widest W per packed tile
+    int ntiles = 0;
+    // arrays
+    struct Arr {
+        Buf ids, ticks;
+        std::vector<int> hticks;  // host mirror of the ticks (request windows)
+        int64_t n = 0;
+        int num_types = 0;
+    };
+    std::vector<Arr> arr;
+    std::mutex amu;  // guards appends against window lookups
+    // requests
+    struct Req {
+        fe_request r;
+        uint64_t ticket;
+        int a = 0, b = 0;  // event index range of the window
+        int status = FE_OK;
+        int state = 0;     // 0 queued, 1 running, 2 done
+        int64_t arrival = 0, admit = 0, done = 0;
+        int round = -1, rsize = 0;
+        int ns = 0, nf = 0;
+        int64_t foot = 0;
+        std::vector<int> up, ex;
+    };
+    std::unordered_map<uint64_t, Req *> reqs;
+    std::deque<Req *> pending;
+    uint64_t next_ticket = 1;
+    // device lanes: one stream and one arena each
+    struct Lane {
+        hipStream_t s = nullptr;
+        hipEvent_t done = nullptr;
+        bool busy = false;
+        std::vector<Req *> reqs;
+        Buf arena, outd, descd, jobsd;
+        int *hout = nullptr;     // pinned results
+        char *hstage = nullptr;  // pinned staging for descriptors and items
+        size_t stage_cap = 0;
+    };
+    std::vector<Lane> lanes;
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    fe_server_stats st{};
+    int round_id = 0;
+    int ncu = 256;
+};
+
+namespace {
+
+// Device state one request needs inside a lane's arena (slot tables, look-
+// back starts, flags, work items, tile lists).
+int64_t req_arena_bytes(const fe_server *sv, int n)
+{
+    int64_t tot = 0;
+    const int span_guess = 1;
+    (void)span_guess;
+    for (const GroupDesc &g : sv->groups) {
+        const int P = std::max(1, (int)std::min<int64_t>(256, (n + sv->cfg.seg_events - 1) /
+                                                             std::max(1, sv->cfg.seg_events)));
+        tot += (int64_t)g.tiles * (P > 1 ? ((int64_t)P * WAVE * KMAX * 8 + (P + 1) * 4 + 4) : 0);
+        tot += (int64_t)g.tiles * P * 8;          // items
+        tot += (int64_t)g.tiles * WAVE * 4 * 2;   // flags
+    }
+    return tot + 4096;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Plan and enqueue one round on a lane.
+int server_launch(fe_server *sv, fe_server::Lane &ln)
+{
+    fe_ctx *c = sv->c;
+    const int R = (int)ln.reqs.size();
+    const int T = sv->ntiles;
+    const int M = sv->M;
+    std::vector<TileDesc> td;
+    td.reserve((size_t)R * T);
+    std::vector<BJob> bj(R);
+    std::vector<int> descN, descD;
+    int64_t lam_off = 0, tbl_off = 0;
+    for (int r = 0; r < R; ++r) {
+        fe_server::Req *q = ln.reqs[r];
+        const fe_server::Arr &A = sv->arr[q->r.array];
+        const int n = q->b - q->a;
+        const int span = n > 0 ? A.hticks[q->b - 1] - A.hticks[q->a] + 1 : 1;
+        bj[r].ids = P<int>(const_cast<Buf &>(A.ids)) + q->a;
+        bj[r].ticks = P<int>(const_cast<Buf &>(A.ticks)) + q->a;
+        bj[r].n = n;
+        bj[r].theta = q->r.theta;
+        bj[r].upper = P<int>(ln.outd) + (int64_t)r * 2 * M;
+        bj[r].exact = P<int>(ln.outd) + (int64_t)r * 2 * M + M;
+        for (const GroupDesc &g : sv->groups) {
+            const int Pn = batch_P(c, n, span, g.wmax, sv->cfg.seg_events);
+            for (int t = g.tile_base; t < g.tile_base + g.tiles; ++t) {
+                TileDesc d;
+                d.job = r;
+                d.P = Pn;
+                d.otile = t;
+                d.rec = sv->tile_rec[t];
+                d.lam = lam_off;
+                d.tbl = tbl_off;
+                if (Pn > 1) {
+                    lam_off += Pn + 1;
+                    tbl_off += (int64_t)Pn * WAVE * KMAX;
+                }
+                td.push_back(d);
+                descN.push_back(g.key / NDCLS + 1);
+                descD.push_back(g.key % NDCLS);
+            }
+        }
+    }
+    const int D = (int)td.size();
+    // work items and tile lists per episode size
+    std::vector<int2> items;
+    std::vector<int> lists;
+    struct LvPlan {
+        int N;
+        int64_t it_rel, n_rel, it_ex[NDCLS], n_ex[NDCLS], pl, npl, pld[NDCLS], npld[NDCLS];
+    };
+    std::vector<LvPlan> lp;
+    for (int N = 1; N <= NMAX; ++N) {
+        std::vector<int> tl;
+        for (int t = 0; t < D; ++t)
+            if (descN[t] == N) tl.push_back(t);
+        if (tl.empty()) continue;
+        LvPlan L{};
+        L.N = N;
+        auto add_items = [&](const std::vector<int> &ts, int64_t &off, int64_t &cnt) {
+            std::vector<std::pair<int64_t, int2>> v;
+            for (int t : ts) {
+                const int Pn = td[t].P;
+                const int64_t cost = (int64_t)bj[td[t].job].n / Pn + 1;
+                for (int p = 0; p < Pn; ++p) v.push_back({cost, make_int2(t, p)});
+            }
+            std::stable_sort(v.begin(), v.end(),
+                             [](const std::pair<int64_t, int2> &a,
+                                const std::pair<int64_t, int2> &b2) { return a.first > b2.first; });
+            off = (int64_t)items.size();
+            cnt = (int64_t)v.size();
+            for (auto &e : v) items.push_back(e.second);
+        };
+        add_items(tl, L.it_rel, L.n_rel);
+        for (int d = 0; d < NDCLS; ++d) {
+            std::vector<int> tdd;
+            for (int t : tl)
+                if (descD[t] == d) tdd.push_back(t);
+            add_items(tdd, L.it_ex[d], L.n_ex[d]);
+            L.pld[d] = (int64_t)lists.size();
+            for (int t : tdd)
+                if (td[t].P > 1) lists.push_back(t);
+            L.npld[d] = (int64_t)lists.size() - L.pld[d];
+        }
+        L.pl = (int64_t)lists.size();
+        for (int t : tl)
+            if (td[t].P > 1) lists.push_back(t);
+        L.npl = (int64_t)lists.size() - L.pl;
+        lp.push_back(L);
+    }
+    // carve the lane arena
+    size_t off = 0;
+    const size_t o_items = off;
+    off = align_up(off + std::max<size_t>(items.size(), 1) * sizeof(int2));
+    const size_t o_lists = off;
+    off = align_up(off + std::max<size_t>(lists.size(), 1) * sizeof(int));
+    const size_t o_lam = off;
+    off = align_up(off + std::max<int64_t>(lam_off, 1) * sizeof(int));
+    const size_t o_tbl = off;
+    off = align_up(off + std::max<int64_t>(tbl_off, 1) * sizeof(int2));
+    const size_t o_fr = off;
+    off = align_up(off + (size_t)D * WAVE * sizeof(int));
+    const size_t o_fx = off;
+    off = align_up(off + (size_t)D * WAVE * sizeof(int));
+    const size_t o_q = off;
+    off = align_up(off + NMAX * (1 + NDCLS) * sizeof(int));
+    if (off > ln.arena.cap) return fail(c, FE_EINTERNAL, "round exceeds its lane arena");
+    char *ar = (char *)ln.arena.p;
+    // staging (pinned): descriptors, jobs, items, lists
+    const size_t sd = align_up(td.size() * sizeof(TileDesc));
+    const size_t sj = align_up(bj.size() * sizeof(BJob));
+    const size_t si = align_up(items.size() * sizeof(int2));
+    const size_t sl = align_up(lists.size() * sizeof(int));
+    const size_t need = sd + sj + si + sl + 1024;
+    if (need > ln.stage_cap) {
+        if (ln.hstage) HIPCHK(c, hipHostFree(ln.hstage));
+        ln.hstage = nullptr;
+        HIPCHK(c, hipHostMalloc((void **)&ln.hstage, need * 2));
+        ln.stage_cap = need * 2;
+    }
+    if (td.size() * sizeof(TileDesc) > ln.descd.cap || bj.size() * sizeof(BJob) > ln.jobsd.cap)
+        return fail(c, FE_EINTERNAL, "round exceeds its descriptor space");
+    std::memcpy(ln.hstage, td.data(), td.size() * sizeof(TileDesc));
+    std::memcpy(ln.hstage + sd, bj.data(), bj.size() * sizeof(BJob));
+    if (!items.empty()) std::memcpy(ln.hstage + sd + sj, items.data(), items.size() * sizeof(int2));
+    if (!lists.empty())
+        std::memcpy(ln.hstage + sd + sj + si, lists.data(), lists.size() * sizeof(int));
+    hipStream_t s = ln.s;
+    HIPCHK(c, hipMemcpyAsync(ln.descd.p, ln.hstage, td.size() * sizeof(TileDesc),
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(ln.jobsd.p, ln.hstage + sd, bj.size() * sizeof(BJob),
+                             hipMemcpyHostToDevice, s));
+    if (!items.empty())
+        HIPCHK(c, hipMemcpyAsync(ar + o_items, ln.hstage + sd + sj, items.size() * sizeof(int2),
+                                 hipMemcpyHostToDevice, s));
+    if (!lists.empty())
+        HIPCHK(c, hipMemcpyAsync(ar + o_lists, ln.hstage + sd + sj + si,
+                                 lists.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    BatchDev d;
+    d.tiles = (const TileDesc *)ln.descd.p;
+    d.jobs = (const BJob *)ln.jobsd.p;
+    d.pk = P<int>(sv->pk);
+    d.orig = P<int>(sv->origd);
+    d.lam = (int *)(ar + o_lam);
+    d.tbl = (int2 *)(ar + o_tbl);
+    d.status = P<int>(c->status);
+    int *lists_d = (int *)(ar + o_lists);
+    int *fr = (int *)(ar + o_fr), *fx = (int *)(ar + o_fx), *qc = (int *)(ar + o_q);
+    const int grid = std::max(1, sv->ncu * sv->cfg.waves_per_cu / WPB);
+    launch_fill(qc, 0, NMAX * (1 + NDCLS), s);
+    int q = 0;
+    for (const LvPlan &L : lp) {
+        launch_clear_flags(lists_d + L.pl, (int)L.npl, fr, fx, s);
+        launch_plan_batch(d.tiles, d.jobs, P<int>(sv->tileWd), lists_d + L.pl, (int)L.npl, d.lam,
+                          s);
+        d.items = (const int2 *)(ar + o_items) + L.it_rel;
+        d.nitems = (int)L.n_rel;
+        d.qctr = qc + q++;
+        d.flags = fr;
+        launch_persist(L.N, false, 0, d, grid, s);
+        launch_concat_batch(d, lists_d + L.pl, (int)L.npl, false, s);
+        launch_persist_fixup(L.N, false, 0, d, lists_d + L.pl, (int)L.npl, s);
+        d.flags = fx;
+        for (int dd = 0; dd < NDCLS; ++dd) {
+            if (!L.n_ex[dd]) continue;
+            d.items = (const int2 *)(ar + o_items) + L.it_ex[dd];
+            d.nitems = (int)L.n_ex[dd];
+            d.qctr = qc + q++;
+            launch_persist(L.N, true, dd, d, grid, s);
+        }
+        launch_concat_batch(d, lists_d + L.pl, (int)L.npl, true, s);
+        for (int dd = 0; dd < NDCLS; ++dd)
+            if (L.npld[dd])
+                launch_persist_fixup(L.N, true, dd, d, lists_d + L.pld[dd], (int)L.npld[dd], s);
+    }
+    HIPCHK(c, hipMemcpyAsync(ln.hout, ln.outd.p, (size_t)R * 2 * M * sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipEventRecord(ln.done, s));
+    HIPCHK(c, hipGetLastError());
+    return FE_OK;
+}
+
+void server_loop(fe_server *sv)
+{
+    fe_ctx *c = sv->c;
+    (void)hipSetDevice(c->device);
+    const int64_t lane_budget = std::max<int64_t>(1, sv->cfg.hbm_budget / sv->cfg.max_inflight);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        bool progressed = false;
+        // completions
+        for (auto &ln : sv->lanes) {
+            if (!ln.busy) continue;
+            const hipError_t e = hipEventQuery(ln.done);
+            if (e == hipErrorNotReady) continue;
+            const int64_t now = steady_ns();
+            for (size_t r = 0; r < ln.reqs.size(); ++r) {
+                fe_server::Req *q = ln.reqs[r];
+                if (e != hipSuccess) {
+                    q->status = FE_EDEVICE;
+                } else {
+                    const int *u = ln.hout + r * 2 * (size_t)sv->M;
+                    q->up.assign(u, u + sv->M);
+                    q->ex.assign(u + sv->M, u + 2 * (size_t)sv->M);
+                    int ns = 0, nf = 0;
+                    for (int m = 0; m < sv->M; ++m) {
+                        ns += q->up[m] >= q->r.theta;
+                        nf += q->ex[m] >= q->r.theta;
+                    }
+                    q->ns = ns;
+                    q->nf = nf;
+                }
+                q->done = now;
+                q->state = 2;
+                sv->st.completed++;
+            }
+            ln.reqs.clear();
+            ln.busy = false;
+            progressed = true;
+        }
+        if (progressed) sv->cv.notify_all();
+        // admission into a free lane
+        int inflight = 0;
+        for (auto &ln : sv->lanes) inflight += ln.busy;
+        sv->st.max_inflight_seen = std::max(sv->st.max_inflight_seen, inflight);
+        fe_server::Lane *free_lane = nullptr;
+        for (auto &ln : sv->lanes)
+            if (!ln.busy) {
+                free_lane = &ln;
+                break;
+            }
+        if (free_lane && !sv->pending.empty()) {
+            int64_t used = 0;
+            const int64_t now = steady_ns();
+            while (!sv->pending.empty() && (int)free_lane->reqs.size() < sv->cfg.max_round) {
+                fe_server::Req *q = sv->pending.front();
+                if (!free_lane->reqs.empty() && used + q->foot > lane_budget) break;
+                sv->pending.pop_front();
+                used += q->foot;
+                q->state = 1;
+                q->admit = now;
+                free_lane->reqs.push_back(q);
+            }
+            const int rid = sv->round_id++;
+            for (auto *q : free_lane->reqs) {
+                q->round = rid;
+                q->rsize = (int)free_lane->reqs.size();
+            }
+            sv->st.rounds++;
+            sv->st.largest_round = std::max<int32_t>(sv->st.largest_round,
+                                                     (int32_t)free_lane->reqs.size());
+            free_lane->busy = true;
+            lk.unlock();
+            int rc;
+            {
+                std::lock_guard<std::mutex> ag(sv->amu);
+                rc = server_launch(sv, *free_lane);
+            }
+            lk.lock();
+            if (rc != FE_OK) {
+                for (auto *q : free_lane->reqs) {
+                    q->status = rc;
+                    q->state = 2;
+                    q->done = steady_ns();
+                    sv->st.completed++;
+                }
+                free_lane->reqs.clear();
+                free_lane->busy = false;
+                sv->cv.notify_all();
+            }
+            continue;
+        }
+        bool any_busy = false;
+        for (auto &ln : sv->lanes) any_busy |= ln.busy;
+        if (sv->stop && !any_busy && sv->pending.empty()) break;
+        if (any_busy) {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        } else {
+            sv->cv.wait_for(lk, std::chrono::milliseconds(2));
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int fe_server_create(fe_ctx *c, const fe_server_config *cfg, const int32_t *num_types,
+                                const int32_t *types, const int32_t *len, const int32_t *lo,
+                                const int32_t *hi, int32_t M, int32_t nmax, fe_server **out)
+{
+    int rc;
+    if (!c || !cfg || !out || !num_types) return FE_EINVAL;
+    *out = nullptr;
+    if (cfg->n_arrays < 1 || cfg->capacity < 1 || cfg->capacity >= ((int64_t)1 << 31) ||
+        cfg->hbm_budget < 1 || cfg->max_inflight < 1 || cfg->max_inflight > 16 ||
+        cfg->max_round < 1 || cfg->seg_events < 0 || cfg->waves_per_cu < 0)
+        return fail(c, FE_EINVAL, "bad server configuration");
+    if (M < 1) return fail(c, FE_EINVAL, "a server needs at least one candidate");
+    if ((rc = check_cands(c, types, len, lo, hi, M, nmax))) return rc;
+    int maxtypes = 0;
+    for (int a = 0; a < cfg->n_arrays; ++a) {
+        if (num_types[a] < 1) return fail(c, FE_EINVAL, "num_types must be positive");
+        maxtypes = std::max(maxtypes, num_types[a]);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    fe_server *sv = new (std::nothrow) fe_server();
+    if (!sv) return fail(c, FE_ENOMEM, "host allocation failed");
+    sv->c = c;
+    sv->cfg = *cfg;
+    if (!sv->cfg.seg_events) sv->cfg.seg_events = 16384;
+    if (!sv->cfg.waves_per_cu) sv->cfg.waves_per_cu = 16;
+    sv->M = M;
+    (void)hipDeviceGetAttribute(&sv->ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+    auto bail = [&](int code) {
+        fe_server_destroy(sv);
+        return code;
+    };
+    // resident candidates: checked on the host, packed once
+    const int nm = nmax, hm = std::max(nm - 1, 1);
+    std::vector<int> ty((size_t)M * nm), ln(M), lov((size_t)M * hm), hiv((size_t)M * hm);
+    HIPCHK(c, hipMemcpy(ty.data(), types, ty.size() * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(ln.data(), len, ln.size() * sizeof(int), hipMemcpyDeviceToHost));
+    if (nm > 1) {
+        HIPCHK(c, hipMemcpy(lov.data(), lo, (size_t)M * (nm - 1) * sizeof(int), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(hiv.data(), hi, (size_t)M * (nm - 1) * sizeof(int), hipMemcpyDeviceToHost));
+    }
+    std::vector<int> rec, orig, tileW;
+    for (int N = 1; N <= nm; ++N) {
+        Episodes C;
+        C.m = N;
+        std::vector<int> back;
+        for (int m = 0; m < M; ++m) {
+            const int L = ln[m];
+            if (L < 1 || L > nm) return bail(fail(c, FE_EINVAL, "bad len"));
+            if (L != N) continue;
+            int64_t W = 0;
+            for (int k = 0; k < N; ++k) {
+                const int t = ty[(size_t)m * nm + k];
+                if (t < 0 || t >= maxtypes) return bail(fail(c, FE_EINVAL, "type out of range"));
+                C.key.push_back(t);
+                if (k < N - 1) {
+                    const int l = lov[(size_t)m * (nm - 1) + k], h = hiv[(size_t)m * (nm - 1) + k];
+                    if (l < 0 || l >= h || h >= TICK_LIMIT || h / (h - l + 1) >= 8)
+                        return bail(fail(c, FE_EINVAL, "bad interval"));
+                    W += h;
+                    C.key.push_back(l);
+                    C.key.push_back(h);
+                }
+            }
+            if (W >= TICK_LIMIT) return bail(fail(c, FE_EINVAL, "W too large"));
+            back.push_back(m);
+        }
+        if (back.empty()) continue;
+        std::vector<int> order(back.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+        HostPack hp;
+        host_pack(C, order, true, hp);
+        for (GroupDesc gd : hp.groups) {
+            gd.tile_base += sv->ntiles;
+            gd.rec_base += (int64_t)rec.size();
+            for (int t = 0; t < gd.tiles; ++t) {
+                sv->tile_rec.push_back(gd.rec_base + (int64_t)t * rec_ints(N));
+                sv->tile_key.push_back(gd.key);
+            }
+            sv->groups.push_back(gd);
+        }
+        rec.insert(rec.end(), hp.rec.begin(), hp.rec.end());
+        for (int o : hp.orig) orig.push_back(o < 0 ? -1 : back[o]);
+        tileW.insert(tileW.end(), hp.tileW.begin(), hp.tileW.end());
+        sv->ntiles += hp.tiles;
+    }
+    if ((rc = ensure(c, sv->pk, rec.size() * sizeof(int)))) return bail(rc);
+    if ((rc = ensure(c, sv->origd, orig.size() * sizeof(int)))) return bail(rc);
+    if ((rc = ensure(c, sv->tileWd, tileW.size() * sizeof(int)))) return bail(rc);
+    HIPCHK(c, hipMemcpy(sv->pk.p, rec.data(), rec.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(sv->origd.p, orig.data(), orig.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(sv->tileWd.p, tileW.data(), tileW.size() * sizeof(int),
+                        hipMemcpyHostToDevice));
+    // arrays
+    sv->arr.resize(cfg->n_arrays);
+    for (int a = 0; a < cfg->n_arrays; ++a) {
+        sv->arr[a].num_types = num_types[a];
+        if ((rc = ensure(c, sv->arr[a].ids, cfg->capacity * sizeof(int)))) return bail(rc);
+        if ((rc = ensure(c, sv->arr[a].ticks, cfg->capacity * sizeof(int)))) return bail(rc);
+        sv->arr[a].hticks.reserve(std::min<int64_t>(cfg->capacity, 1 << 24));
+    }
+    // lanes: stream, completion event, arena sized to the lane's budget
+    const int64_t lane_budget = std::max<int64_t>(1, cfg->hbm_budget / cfg->max_inflight);
+    const int64_t max_one = req_arena_bytes(sv, (int)cfg->capacity);
+    const int64_t arena = std::max<int64_t>(lane_budget, max_one) + (64 << 10);
+    sv->lanes.resize(cfg->max_inflight);
+    for (auto &L : sv->lanes) {
+        HIPCHK(c, hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
+        if ((rc = ensure(c, L.arena, arena))) return bail(rc);
+        if ((rc = ensure(c, L.outd, (size_t)cfg->max_round * 2 * M * sizeof(int)))) return bail(rc);
+        if ((rc = ensure(c, L.descd, (size_t)cfg->max_round * sv->ntiles * sizeof(TileDesc))))
+            return bail(rc);
+        if ((rc = ensure(c, L.jobsd, (size_t)cfg->max_round * sizeof(BJob)))) return bail(rc);
+        HIPCHK(c, hipHostMalloc((void **)&L.hout, (size_t)cfg->max_round * 2 * M * sizeof(int)));
+    }
+    sv->th = std::thread(server_loop, sv);
+    *out = sv;
+    return FE_OK;
+}
+
+extern "C" int fe_server_append(fe_server *sv, int32_t a, const int32_t *ids, const int32_t *ticks,
+                                int64_t n)
+{
+    if (!sv) return FE_EINVAL;
+    fe_ctx *c = sv->c;
+    if (a < 0 || a >= (int)sv->arr.size() || n < 0 || (n > 0 && (!ids || !ticks)))
+        return fail(c, FE_EINVAL, "bad append");
+    if (n == 0) return FE_OK;
+    std::lock_guard<std::mutex> ag(sv->amu);
+    fe_server::Arr &A = sv->arr[a];
+    if (A.n + n > sv->cfg.capacity) return fail(c, FE_ENOMEM, "array %d buffer full", a);
+    int prev = A.n ? A.hticks.back() : 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (ids[i] < 0 || ids[i] >= A.num_types || ticks[i] < 0 || ticks[i] >= TICK_LIMIT)
+            return fail(c, FE_ERANGE, "event out of range");
+        if ((A.n || i) && ticks[i] < prev) return fail(c, FE_EUNSORTED, "events out of order");
+        prev = ticks[i];
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpy(P<int>(A.ids) + A.n, ids, n * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(P<int>(A.ticks) + A.n, ticks, n * sizeof(int), hipMemcpyHostToDevice));
+    A.hticks.insert(A.hticks.end(), ticks, ticks + n);
+    A.n += n;
+    return FE_OK;
+}
+
+extern "C" int fe_server_submit(fe_server *sv, const fe_request *rq, uint64_t *ticket)
+{
+    if (!sv || !rq || !ticket) return FE_EINVAL;
+    fe_ctx *c = sv->c;
+    if (rq->array < 0 || rq->array >= (int)sv->arr.size() || rq->t_end < rq->t_begin)
+        return fail(c, FE_EINVAL, "bad request");
+    fe_server::Req *q = new (std::nothrow) fe_server::Req();
+    if (!q) return fail(c, FE_ENOMEM, "host allocation failed");
+    q->r = *rq;
+    q->arrival = rq->arrival_ns ? rq->arrival_ns : steady_ns();
+    {
+        std::lock_guard<std::mutex> ag(sv->amu);
+        const std::vector<int> &h = sv->arr[rq->array].hticks;
+        q->a = (int)(std::lower_bound(h.begin(), h.end(), rq->t_begin) - h.begin());
+        q->b = (int)(std::lower_bound(h.begin(), h.end(), rq->t_end) - h.begin());
+    }
+    q->foot = req_arena_bytes(sv, q->b - q->a) + 2 * (int64_t)sv->M * 4;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    q->ticket = sv->next_ticket++;
+    sv->reqs[q->ticket] = q;
+    sv->st.submitted++;
+    if (q->foot > sv->cfg.hbm_budget) {
+        q->status = FE_ENOMEM;
+        q->state = 2;
+        q->done = steady_ns();
+        sv->st.rejected++;
+        sv->st.completed++;
+    } else {
+        sv->pending.push_back(q);
+    }
+    *ticket = q->ticket;
+    sv->cv.notify_all();
+    return FE_OK;
+}
+
+namespace {
+void fill_response(const fe_server::Req *q, fe_response *out)
+{
+    out->status = q->status;
+    out->n_events = q->b - q->a;
+    out->n_survivors = q->ns;
+    out->n_frequent = q->nf;
+    out->upper = q->up.empty() ? nullptr : q->up.data();
+    out->exact = q->ex.empty() ? nullptr : q->ex.data();
+    out->arrival_ns = q->arrival;
+    out->admit_ns = q->admit;
+    out->done_ns = q->done;
+    out->round = q->round;
+    out->round_size = q->rsize;
+}
+}  // namespace
+
+extern "C" int fe_server_poll(fe_server *sv, uint64_t ticket, fe_response *out)
+{
+    if (!sv || !out) return FE_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) return FE_EINVAL;
+    if (it->second->state != 2) return FE_EBUSY;
+    fill_response(it->second, out);
+    return FE_OK;
+}
+
+extern "C" int fe_server_wait(fe_server *sv, uint64_t ticket, fe_response *out)
+{
+    if (!sv || !out) return FE_EINVAL;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) return FE_EINVAL;
+    fe_server::Req *q = it->second;
+    sv->cv.wait(lk, [&] { return q->state == 2; });
+    fill_response(q, out);
+    return FE_OK;
+}
+
+extern "C" int fe_server_release(fe_server *sv, uint64_t ticket)
+{
+    if (!sv) return FE_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end() || it->second->state != 2) return FE_EINVAL;
+    delete it->second;
+    sv->reqs.erase(it);
+    return FE_OK;
+}
+
+extern "C" int fe_server_get_stats(fe_server *sv, fe_server_stats *out)
+{
+    if (!sv || !out) return FE_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    *out = sv->st;
+    return FE_OK;
+}
+
+extern "C" int fe_server_destroy(fe_server *sv)
+{
+    if (!sv) return FE_EINVAL;
+    fe_ctx *c = sv->c;
+    if (sv->th.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->stop = true;
+            for (auto *q : sv->pending) {
+                q->status = FE_EINVAL;
+                q->state = 2;
+            }
+            sv->pending.clear();
+        }
+        sv->cv.notify_all();
+        sv->th.join();
+    }
+    (void)hipSetDevice(c->device);
+    for (auto &L : sv->lanes) {
+        if (L.s) (void)hipStreamSynchronize(L.s);
+        Buf *bs[] = {&L.arena, &L.outd, &L.descd, &L.jobsd};
+        for (Buf *x : bs)
+            if (x->p) (void)hipFree(x->p);
+        if (L.hout) (void)hipHostFree(L.hout);
+        if (L.hstage) (void)hipHostFree(L.hstage);
+        if (L.done) (void)hipEventDestroy(L.done);
+        if (L.s) (void)hipStreamDestroy(L.s);
+    }
+    for (auto &A : sv->arr) {
+        if (A.ids.p) (void)hipFree(A.ids.p);
+        if (A.ticks.p) (void)hipFree(A.ticks.p);
+    }
+    Buf *bs[] = {&sv->pk, &sv->origd, &sv->tileWd};
+    for (Buf *x : bs)
+        if (x->p) (void)hipFree(x->p);
+    for (auto &kv : sv->reqs) delete kv.second;
+    delete sv;
+    return FE_OK;
 }

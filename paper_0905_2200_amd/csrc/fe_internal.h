@@ -59,6 +59,7 @@ struct BJob {
 struct TileDesc {
     int job;      // recording
     int P;        // segments of the tile's group
+    int otile;    // packed tile (record, orig and tileW index); may be shared
     int64_t rec;  // int offset of the tile record in pk
     int64_t tbl;  // int2 offset of the tile's slot tables [P][64][KMAX]
     int64_t lam;  // int offset of the tile's lam[P+1]

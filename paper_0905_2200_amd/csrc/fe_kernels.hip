@@ -289,7 +289,7 @@ __global__ void k_plan_batch(const TileDesc *tiles, const BJob *jobs, const int 
     const int tile = ptiles[w];
     const TileDesc td = tiles[tile];
     const BJob jb = jobs[td.job];
-    const int n = jb.n, P = td.P, W = tileW[tile];
+    const int n = jb.n, P = td.P, W = tileW[td.otile];
     for (int p = lane; p <= P; p += WAVE) {
         int v;
         if (p == 0) {
@@ -351,7 +351,7 @@ __global__ void k_concat_batch(BatchDev b, const int *ctiles, int nct, int exact
     const TileDesc td = b.tiles[tile];
     const BJob jb = b.jobs[td.job];
     const int c = tile * WAVE + lane;
-    const int o = b.orig[c];
+    const int o = b.orig[(int64_t)td.otile * WAVE + lane];
     if (o < 0) return;
     int *out = exact ? jb.exact : jb.upper;
     if (exact && jb.upper[o] < jb.theta) {

@@ -523,7 +523,7 @@ __global__ __launch_bounds__(WAVE *WPB) void k_persist(BatchDev b)
         const TileDesc td = b.tiles[tile];
         const BJob jb = b.jobs[uniform(td.job)];
         const int c = tile * WAVE + lane;
-        const int o = b.orig[c];
+        const int o = b.orig[(int64_t)uniform(td.otile) * WAVE + lane];
         int *out = EXACT ? jb.exact : jb.upper;
         bool valid = o >= 0;
         if (EXACT) valid = valid && jb.upper[o] >= jb.theta;
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(WAVE *WPB) void k_persist_fixup(BatchDev b, const i
     const TileDesc td = b.tiles[tile];
     const BJob jb = b.jobs[uniform(td.job)];
     const int c = tile * WAVE + lane;
-    const int o = b.orig[c];
+    const int o = b.orig[(int64_t)uniform(td.otile) * WAVE + lane];
     bool f = o >= 0 && b.flags[c] != 0;
     if (EXACT) f = f && jb.upper[o] >= jb.theta;
     if (__ballot(f) == 0) return;

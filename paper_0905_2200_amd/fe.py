@@ -26,7 +26,9 @@ EXPORTS = ["fe_create", "fe_destroy", "fe_last_error", "fe_sync", "fe_set_param"
            "fe_get_param", "fe_validate", "fe_count", "fe_count_two_pass", "fe_mine",
            "fe_result_free", "fe_get_stats", "fe_get_kernel_stats", "fe_reset_kernel_stats",
            "fe_batch_create", "fe_batch_run", "fe_batch_autotune", "fe_batch_set_tuning",
-           "fe_batch_get_tuning", "fe_batch_destroy", "fe_count_batched"]
+           "fe_batch_get_tuning", "fe_batch_destroy", "fe_count_batched",
+           "fe_server_create", "fe_server_append", "fe_server_submit", "fe_server_poll",
+           "fe_server_wait", "fe_server_release", "fe_server_get_stats", "fe_server_destroy"]
 
 
 class FeError(RuntimeError):
@@ -71,6 +73,33 @@ class _Tuning(ctypes.Structure):
                 ("run_ms", ctypes.c_double)]
 
 
+class _ServerCfg(ctypes.Structure):
+    _fields_ = [("n_arrays", ctypes.c_int32), ("capacity", ctypes.c_int64),
+                ("hbm_budget", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("max_round", ctypes.c_int32), ("seg_events", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("array", ctypes.c_int32), ("t_begin", ctypes.c_int32), ("t_end", ctypes.c_int32),
+                ("theta", ctypes.c_int32), ("arrival_ns", ctypes.c_int64)]
+
+
+class _Response(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_events", ctypes.c_int32),
+                ("n_survivors", ctypes.c_int32), ("n_frequent", ctypes.c_int32),
+                ("upper", ctypes.POINTER(ctypes.c_int32)), ("exact", ctypes.POINTER(ctypes.c_int32)),
+                ("arrival_ns", ctypes.c_int64), ("admit_ns", ctypes.c_int64),
+                ("done_ns", ctypes.c_int64), ("round", ctypes.c_int32),
+                ("round_size", ctypes.c_int32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("rounds", ctypes.c_int64),
+                ("largest_round", ctypes.c_int32), ("max_inflight_seen", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -109,6 +138,16 @@ def lib():
         "fe_batch_get_tuning": ([V, ctypes.POINTER(_Tuning)], ctypes.c_int),
         "fe_batch_destroy": ([V], ctypes.c_int),
         "fe_count_batched": ([CTX, I32, ctypes.POINTER(_Job)], ctypes.c_int),
+        "fe_server_create": ([CTX, ctypes.POINTER(_ServerCfg), V, V, V, V, V, I32, I32,
+                              ctypes.POINTER(V)], ctypes.c_int),
+        "fe_server_append": ([V, I32, V, V, I64], ctypes.c_int),
+        "fe_server_submit": ([V, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)],
+                             ctypes.c_int),
+        "fe_server_poll": ([V, ctypes.c_uint64, ctypes.POINTER(_Response)], ctypes.c_int),
+        "fe_server_wait": ([V, ctypes.c_uint64, ctypes.POINTER(_Response)], ctypes.c_int),
+        "fe_server_release": ([V, ctypes.c_uint64], ctypes.c_int),
+        "fe_server_get_stats": ([V, ctypes.POINTER(_ServerStats)], ctypes.c_int),
+        "fe_server_destroy": ([V], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -355,6 +394,82 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             lib().fe_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Window-counting service (continuous batching of requests into rounds
+    admitted by device-memory footprint, several rounds in flight).  The
+    resident candidate set is a host dict (synth.pack layout); events are
+    appended per array from host arrays; results come back as numpy."""
+
+    def __init__(self, ctx, cand, num_types, capacity, hbm_budget, max_inflight=3, max_round=64,
+                 seg_events=0, waves_per_cu=0):
+        self.ctx = ctx
+        c = ctx.cand_tensors(cand)
+        self._cand = c
+        self.M = c["M"]
+        nt = np.ascontiguousarray(np.asarray(num_types, np.int32))
+        cfg = _ServerCfg(len(nt), int(capacity), int(hbm_budget), int(max_inflight),
+                         int(max_round), int(seg_events), int(waves_per_cu))
+        h = ctypes.c_void_p()
+        ctx.torch.cuda.synchronize(ctx.device)
+        ctx._check(lib().fe_server_create(ctx.h, ctypes.byref(cfg),
+                                          nt.ctypes.data_as(ctypes.c_void_p),
+                                          _ptr(c["types"]), _ptr(c["len"]), _ptr(c["lo"]),
+                                          _ptr(c["hi"]), self.M, c["nmax"], ctypes.byref(h)))
+        self.h = h
+
+    def append(self, array, ids, ticks):
+        ids = np.ascontiguousarray(np.asarray(ids, np.int32))
+        ticks = np.ascontiguousarray(np.asarray(ticks, np.int32))
+        self.ctx._check(lib().fe_server_append(self.h, int(array),
+                                               ids.ctypes.data_as(ctypes.c_void_p),
+                                               ticks.ctypes.data_as(ctypes.c_void_p), ids.size))
+
+    def submit(self, array, t_begin, t_end, theta, arrival_ns=0):
+        r = _Request(int(array), int(t_begin), int(t_end), int(theta), int(arrival_ns))
+        t = ctypes.c_uint64()
+        self.ctx._check(lib().fe_server_submit(self.h, ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    def _resp(self, r, copy):
+        d = {k: getattr(r, k) for k, _ in _Response._fields_ if k not in ("upper", "exact")}
+        if copy and r.upper:
+            d["upper"] = np.ctypeslib.as_array(r.upper, shape=(self.M,)).copy()
+            d["exact"] = np.ctypeslib.as_array(r.exact, shape=(self.M,)).copy()
+        return d
+
+    def poll(self, ticket, copy=True):
+        r = _Response()
+        rc = lib().fe_server_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(r))
+        if rc == FE_EBUSY:
+            return None
+        self.ctx._check(rc)
+        return self._resp(r, copy)
+
+    def wait(self, ticket, copy=True):
+        r = _Response()
+        self.ctx._check(lib().fe_server_wait(self.h, ctypes.c_uint64(ticket), ctypes.byref(r)))
+        return self._resp(r, copy)
+
+    def release(self, ticket):
+        self.ctx._check(lib().fe_server_release(self.h, ctypes.c_uint64(ticket)))
+
+    def stats(self):
+        s = _ServerStats()
+        self.ctx._check(lib().fe_server_get_stats(self.h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in _ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fe_server_destroy(self.h)
             self.h = None
 
     def __del__(self):
