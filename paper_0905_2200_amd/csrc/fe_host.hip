@@ -47,7 +47,7 @@ struct fe_ctx {
     int64_t param[5] = {0, 4096, 1024, 1, 0};
     fe_stats stats{};
     // workspace
-    Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small;
+    Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
     Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn;
     int *host = nullptr;  // pinned host staging for small readbacks
     size_t host_cap = 0;
@@ -261,6 +261,13 @@ int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo 
 {
     hipStream_t s = c->stream;
     int rc;
+    const unsigned long long *cmask = nullptr;
+    if (si.n > 0) {
+        if ((rc = ensure(c, c->cmask, (size_t)((si.n + 7) / 8) * sizeof(unsigned long long))))
+            return rc;
+        launch_chunkmask(ids, si.n, (unsigned long long *)c->cmask.p, s);
+        cmask = (const unsigned long long *)c->cmask.p;
+    }
     for (const GroupDesc &gd : groups) {
         const int k = gd.key;
         const int N = k / NDCLS + 1, dcls = k % NDCLS;
@@ -273,6 +280,7 @@ int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo 
         g.orig = P<int>(c->orig) + (int64_t)gd.tile_base * WAVE;
         g.out = out;
         g.status = P<int>(c->status);
+        g.cmask = cmask;
         g.tiles = tiles;
         g.lam = nullptr;
         g.tbl = nullptr;
@@ -532,7 +540,7 @@ extern "C" int fe_destroy(fe_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     Buf *bufs[] = {&c->keys, &c->hist, &c->wmax, &c->fill, &c->pk,    &c->orig,  &c->tileW,
-                   &c->lam,  &c->tbl,  &c->flags, &c->sel, &c->nsel,  &c->status, &c->small,
+                   &c->lam,  &c->tbl,  &c->flags, &c->sel, &c->nsel,  &c->status, &c->small, &c->cmask,
                    &c->mtypes, &c->mlen, &c->mlo, &c->mhi, &c->mup, &c->mex, &c->msel, &c->mn};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);

@@ -42,6 +42,7 @@ struct MapGroup {
     int *flags;        // [tiles*64] slot overflow flags (P > 1)
     int *out;          // [M] per original candidate
     int *status;
+    const unsigned long long *cmask;  // type masks of aligned 8-event chunks, or null
     int tiles;
     int P;
 };
@@ -110,6 +111,7 @@ void launch_compact(const int *vals, int M, int theta, int *pruned_out,
 void launch_select(const int *vals, const int *src, int M, int theta, int *out, hipStream_t s);
 void launch_gather2(const int *a, const int *b, const int *sel, const int *nsel, int M,
                     int *out_a, int *out_b, hipStream_t s);
+void launch_chunkmask(const int *ids, int n, unsigned long long *out, hipStream_t s);
 void launch_histogram(const int *ids, int n, int num_types, int *hist,
                       hipStream_t s);
 

@@ -518,6 +518,24 @@ void launch_gather2(const int *a, const int *b, const int *sel, const int *nsel,
                        out_b);
 }
 
+// out[c] = OR over the events of chunk c (indices 8c..8c+7) of 1 << (id & 63)
+__global__ void k_chunkmask(const int *__restrict__ ids, int n, unsigned long long *out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c * 8 >= n) return;
+    unsigned long long m = 0;
+    const int e = c * 8 + 8 < n ? c * 8 + 8 : n;
+    for (int i = c * 8; i < e; ++i) m |= 1ull << (ids[i] & 63);
+    out[c] = m;
+}
+
+void launch_chunkmask(const int *ids, int n, unsigned long long *out, hipStream_t s)
+{
+    if (n <= 0) return;
+    const int chunks = (n + 7) / 8;
+    hipLaunchKernelGGL(k_chunkmask, dim3((chunks + 255) / 256), dim3(256), 0, s, ids, n, out);
+}
+
 // ------------------------------------------------------------------ level 1
 __global__ void k_histogram(const int *__restrict__ ids, int n, int num_types, int *hist)
 {

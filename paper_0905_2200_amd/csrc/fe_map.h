@@ -100,6 +100,12 @@ template <int N> struct Relaxed {
             return comp;
         }
     }
+    // Event whose type matches none of nodes 0..N-2: only the last node acts.
+    __device__ __forceinline__ bool step_last(int e, int t, const Cand<N> &c) const
+    {
+        if constexpr (N == 1) return e == c.ty[0];
+        else return (e == c.ty[N - 1]) & (t <= dl[N - 2]);
+    }
     // Nodes 0..N-2 have wave-uniform types u.ty: scalar tests, rare updates.
     __device__ __forceinline__ bool step_u(int e, int t, const Cand<N> &c, const Prefix<N> &u,
                                            int *)
@@ -183,6 +189,11 @@ template <int N, int D> struct Exact {
             return comp;
         }
     }
+    __device__ __forceinline__ bool step_last(int e, int t, const Cand<N> &c) const
+    {
+        if constexpr (N == 1) return e == c.ty[0];
+        else return (e == c.ty[N - 1]) & hit(N - 2, t);
+    }
     __device__ __forceinline__ bool step_u(int e, int t, const Cand<N> &c, const Prefix<N> &u,
                                            int *status)
     {
@@ -250,22 +261,63 @@ template <int N, bool EXACT, int D> struct MainRun {
 
     // Bulk of a segment (indices below the next look-back): count every
     // completion.  UNI: the tile shares the types of nodes 0..N-2.
-    template <bool UNI, bool NOTE>
-    __device__ void body(cptr ids, cptr ticks, int b, int e, const Cand<N> &c,
-                         const Prefix<N> &u, int *status)
+    __device__ __forceinline__ void complete(bool comp, int idx, int t, bool note_it)
     {
-        if (uniform(b) >= uniform(e)) return;
-        for_events<U>(ids, ticks, b, e, [&](int ev, int t, int idx) {
-            bool comp;
-            if constexpr (UNI) comp = m.step_u(ev, t, c, u, status);
-            else comp = m.step(ev, t, c, true, status);
+        if (__builtin_expect(__ballot(comp) != 0, 0)) {
             if (comp) {
                 m.reset();
                 ++cnt;
                 lastx = 0;
-                if constexpr (NOTE) note(idx, t);
+                if (note_it) note(idx, t);
             }
-        });
+        }
+    }
+
+    // Bulk of a segment (indices below the next look-back): count every
+    // completion.  UNI: the tile shares the types of nodes 0..N-2; then,
+    // given per-chunk type masks of the stream (bit (type & 63) of every
+    // event in an aligned chunk of 8), a chunk whose mask misses every
+    // shared type is processed with the last node alone.
+    template <bool UNI, bool NOTE>
+    __device__ void body(cptr ids, cptr ticks, const unsigned long long *cmask, int b, int e,
+                         const Cand<N> &c, const Prefix<N> &u, int *status)
+    {
+        b = uniform(b);
+        e = uniform(e);
+        if (b >= e) return;
+        auto general = [&](int ev, int t, int idx) {
+            bool comp;
+            if constexpr (UNI) comp = m.step_u(ev, t, c, u, status);
+            else comp = m.step(ev, t, c, true, status);
+            complete(comp, idx, t, NOTE);
+        };
+        // (the exact machine keeps the per-event path: splitting its loop in
+        // two grows its state's register copies past the occupancy budget)
+        if constexpr (UNI && !EXACT) {
+            if (cmask) {
+                int i = b;
+                const int a8 = (b + 7) & ~7;
+                for (; i < e && i < a8; ++i) general(ids[i], ticks[i], i);
+                for (; i + 8 <= e; i += 8) {
+                    int ev[8], tv[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) { ev[k] = ids[i + k]; tv[k] = ticks[i + k]; }
+                    const unsigned long long cm =
+                        ((const __attribute__((address_space(4))) unsigned long long *)cmask)[i >> 3];
+                    if ((cm & u.mask) == 0) {
+#pragma unroll
+                        for (int k = 0; k < 8; ++k)
+                            complete(m.step_last(ev[k], tv[k], c), i + k, tv[k], NOTE);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) general(ev[k], tv[k], i + k);
+                    }
+                }
+                for (; i < e; ++i) general(ids[i], ticks[i], i);
+                return;
+            }
+        }
+        for_events<U>(ids, ticks, b, e, general);
     }
 
     // Look-back and tail of a segment: completions count only at idx >= L,
@@ -424,6 +476,7 @@ struct ItemArgs {
     int *flag;       // this lane's slot-overflow flag (P > 1)
     int *out;        // counts, indexed by the candidate's input index
     int *status;
+    const unsigned long long *cmask;  // per aligned 8-event chunk type masks, or null
 };
 
 // Map step of one work item.  o: the lane's candidate index (-1 = padding);
@@ -439,8 +492,8 @@ __device__ __forceinline__ void map_item(const ItemArgs &a, int o, bool valid)
     MainRun<N, EXACT, D> r;
     r.m.reset();
     if (a.P == 1) {
-        if (uni) r.template body<true, false>(a.ids, a.ticks, 0, a.n, cd, u, a.status);
-        else r.template body<false, false>(a.ids, a.ticks, 0, a.n, cd, u, a.status);
+        if (uni) r.template body<true, false>(a.ids, a.ticks, a.cmask, 0, a.n, cd, u, a.status);
+        else r.template body<false, false>(a.ids, a.ticks, a.cmask, 0, a.n, cd, u, a.status);
         if (valid) a.out[o] = r.cnt;
         return;
     }
@@ -456,8 +509,8 @@ __device__ __forceinline__ void map_item(const ItemArgs &a, int o, bool valid)
     // slot 0: the last completion before L lies before lam
     for (int k = 0; k < QREC; ++k) { r.ci[k] = -1; r.ck[k] = 0; r.ct[k] = 0; }
     r.edge(a.ids, a.ticks, lam, L, L, lamn, cd, a.status);
-    if (uni) r.template body<true, true>(a.ids, a.ticks, L, xl, cd, u, a.status);
-    else r.template body<false, true>(a.ids, a.ticks, L, xl, cd, u, a.status);
+    if (uni) r.template body<true, true>(a.ids, a.ticks, a.cmask, L, xl, cd, u, a.status);
+    else r.template body<false, true>(a.ids, a.ticks, a.cmask, L, xl, cd, u, a.status);
     r.edge(a.ids, a.ticks, xl, R, L, lamn, cd, a.status);
     if (valid) a.tb[0] = make_int2(r.cnt, r.lastx < KMAX ? r.lastx : KMAX - 1);
 
@@ -502,6 +555,7 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map(const int *__restrict__ ids_,
     a.flag = P > 1 ? g.flags + c : nullptr;
     a.out = g.out;
     a.status = g.status;
+    a.cmask = g.cmask;
     map_item<N, EXACT, D>(a, o, o >= 0);
 }
 
@@ -542,6 +596,7 @@ __global__ __launch_bounds__(WAVE *WPB) void k_persist(BatchDev b)
         a.flag = b.flags + c;
         a.out = out;
         a.status = b.status;
+        a.cmask = nullptr;
         map_item<N, EXACT, D>(a, o, valid);
     }
 }
