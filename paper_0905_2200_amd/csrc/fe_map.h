@@ -278,7 +278,7 @@ template <int N, bool EXACT, int D> struct MainRun {
     // given per-chunk type masks of the stream (bit (type & 63) of every
     // event in an aligned chunk of 8), a chunk whose mask misses every
     // shared type is processed with the last node alone.
-    template <bool UNI, bool NOTE>
+    template <bool UNI, bool NOTE, bool CHUNK = !EXACT>
     __device__ void body(cptr ids, cptr ticks, const unsigned long long *cmask, int b, int e,
                          const Cand<N> &c, const Prefix<N> &u, int *status)
     {
@@ -291,9 +291,10 @@ template <int N, bool EXACT, int D> struct MainRun {
             else comp = m.step(ev, t, c, true, status);
             complete(comp, idx, t, NOTE);
         };
-        // (the exact machine keeps the per-event path: splitting its loop in
-        // two grows its state's register copies past the occupancy budget)
-        if constexpr (UNI && !EXACT) {
+        // (inside the segmented kernel the exact machine keeps the per-event
+        // path: splitting its loop in two there grows the register copies of
+        // its state past the occupancy budget)
+        if constexpr (UNI && CHUNK) {
             if (cmask) {
                 int i = b;
                 const int a8 = (b + 7) & ~7;
@@ -308,6 +309,12 @@ template <int N, bool EXACT, int D> struct MainRun {
 #pragma unroll
                         for (int k = 0; k < 8; ++k)
                             complete(m.step_last(ev[k], tv[k], c), i + k, tv[k], NOTE);
+                    } else if constexpr (EXACT) {
+                        // rare: events of the shared-prefix types; the exact
+                        // machine reloads them in a rolled loop, which keeps its
+                        // register count (and occupancy) at the clean path's
+#pragma unroll 1
+                        for (int k = i; k < i + 8; ++k) general(ids[k], ticks[k], k);
                     } else {
 #pragma unroll
                         for (int k = 0; k < 8; ++k) general(ev[k], tv[k], i + k);
@@ -559,6 +566,30 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map(const int *__restrict__ ids_,
     map_item<N, EXACT, D>(a, o, o >= 0);
 }
 
+// Whole-stream Map (P = 1, one machine per lane, no segment bookkeeping):
+// the launch used when the tiles alone fill the GPU.
+template <int N, bool EXACT, int D>
+__global__ __launch_bounds__(WAVE *WPB) void k_map1(const int *__restrict__ ids_,
+                                                    const int *__restrict__ ticks_, MapGroup g)
+{
+    const int lane = __lane_id();
+    const int tile = uniform(blockIdx.x * WPB + (threadIdx.x >> 6));
+    if (tile >= g.tiles) return;
+    const int o = g.orig[tile * WAVE + lane];
+    Cand<N> cd;
+    load_cand<N>(cd, g.pk + (int64_t)tile * rec_ints(N), lane);
+    Prefix<N> u;
+    const bool uni = shared_prefix<N>(cd, o >= 0, u);
+    MainRun<N, EXACT, D> r;
+    r.m.reset();
+    if (uni)
+        r.template body<true, false, true>((cptr)ids_, (cptr)ticks_, g.cmask, 0, g.n, cd, u,
+                                           g.status);
+    else
+        r.template body<false, false>((cptr)ids_, (cptr)ticks_, g.cmask, 0, g.n, cd, u, g.status);
+    if (o >= 0) g.out[o] = r.cnt;
+}
+
 // Persistent batched Map: a grid sized to the machine pops (tile, segment)
 // items of many recordings from a queue (heaviest first) until it is empty.
 // In the exact pass only candidates that survived the relaxed pass count;
@@ -690,6 +721,9 @@ template <int N, bool EXACT, int D> void map_n(const MapGroup &g, hipStream_t s,
 {
     if (fix) {
         hipLaunchKernelGGL((k_fixup<N, EXACT, D>), dim3((unsigned)((g.tiles + WPB - 1) / WPB)),
+                           dim3(WAVE * WPB), 0, s, g.ids, g.ticks, g);
+    } else if (g.P == 1) {
+        hipLaunchKernelGGL((k_map1<N, EXACT, D>), dim3((unsigned)((g.tiles + WPB - 1) / WPB)),
                            dim3(WAVE * WPB), 0, s, g.ids, g.ticks, g);
     } else {
         const int64_t items = (int64_t)g.tiles * g.P;
