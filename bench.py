@@ -109,6 +109,8 @@ def main():
                          "window requests from 32 arrays, open-loop Poisson trace")
     ap.add_argument("--trace-s", type=float, default=20.0, help="served: trace length (s)")
     ap.add_argument("--rate", type=float, default=200.0, help="served: requests per second")
+    ap.add_argument("--type-dispatch", type=int, default=1, choices=[0, 1],
+                    help="per-type dispatch for shared-prefix waves (0 = every event)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -139,6 +141,7 @@ def main():
     log("workload: %s; n=%d theta=%d" % (s["name"], n, theta))
 
     ctx = fe.Context(0)
+    ctx.set_param(fe.PARAM_TYPE_DISPATCH, args.type_dispatch)
     ids, ticks = ctx.stream_tensors(s["ids"], s["ticks"])
     torch.cuda.synchronize()
 

@@ -84,8 +84,12 @@ typedef enum fe_param {
     FE_PARAM_MIN_SEG_EVENTS = 2, /* smallest segment the automatic P allows   */
     FE_PARAM_CONCAT_TREE = 3, /* 1 = wave-shuffle tree Concatenate when P >= 16,
                                  0 = per-candidate sequential walk             */
-    FE_PARAM_TIMING = 4      /* 1 = time every kernel launch with HIP events on
+    FE_PARAM_TIMING = 4,     /* 1 = time every kernel launch with HIP events on
                                 the context's stream (fe_get_kernel_stats)     */
+    FE_PARAM_TYPE_DISPATCH = 5 /* 1 (default) = waves whose candidates share
+                                their first N-1 types step only the events of
+                                those types, plus each lane its own last-type
+                                events; 0 = every event through every lane    */
 } fe_param;
 
 typedef struct fe_ctx fe_ctx;

@@ -44,7 +44,7 @@ struct fe_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
-    int64_t param[5] = {0, 4096, 1024, 1, 0};
+    int64_t param[6] = {0, 4096, 1024, 1, 0, 1};
     fe_stats stats{};
     // workspace
     Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
@@ -286,6 +286,7 @@ int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo 
         g.tbl = nullptr;
         g.flags = nullptr;
         g.P = choose_P(c, tiles, si, gd.wmax);
+        g.sparse = c->param[FE_PARAM_TYPE_DISPATCH] != 0;
         c->stats.map_launches++;
         char kname[40];
         snprintf(kname, sizeof kname, "map_%s_n%d_d%d", exact ? "exact" : "relaxed", N,
@@ -580,7 +581,7 @@ extern "C" int fe_sync(fe_ctx *c)
 extern "C" int fe_set_param(fe_ctx *c, int param, int64_t value)
 {
     if (!c) return FE_EINVAL;
-    if (param < 0 || param > 4 || value < 0) return fail(c, FE_EINVAL, "bad parameter");
+    if (param < 0 || param > 5 || value < 0) return fail(c, FE_EINVAL, "bad parameter");
     if (param == FE_PARAM_TARGET_WAVES && value == 0) return fail(c, FE_EINVAL, "bad parameter");
     c->param[param] = value;
     return FE_OK;
@@ -588,7 +589,7 @@ extern "C" int fe_set_param(fe_ctx *c, int param, int64_t value)
 
 extern "C" int fe_get_param(const fe_ctx *c, int param, int64_t *value)
 {
-    if (!c || !value || param < 0 || param > 4) return FE_EINVAL;
+    if (!c || !value || param < 0 || param > 5) return FE_EINVAL;
     *value = c->param[param];
     return FE_OK;
 }

@@ -45,6 +45,7 @@ struct MapGroup {
     const unsigned long long *cmask;  // type masks of aligned 8-event chunks, or null
     int tiles;
     int P;
+    int sparse;  // shared-prefix waves use per-type dispatch
 };
 
 // Batched counting (many recordings): one descriptor per recording and per

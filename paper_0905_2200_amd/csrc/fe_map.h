@@ -327,6 +327,83 @@ template <int N, bool EXACT, int D> struct MainRun {
         for_events<U>(ids, ticks, b, e, general);
     }
 
+    // Bulk of a segment for a shared-prefix wave by per-type dispatch (the
+    // paper's CPU counter keeps, per event type, the machines waiting on it;
+    // this is the wave form of that idea).  Events come in blocks of 64, one
+    // per lane (vector loads).  "Prefix events" -- those whose type hash is
+    // that of a shared node -- form a wave-uniform set and are stepped by the
+    // whole wave in stream order.  Between two prefix events a lane's lists
+    // change only through its own last node: the first of its last-type
+    // events there that passes the hop test completes (and empties the
+    // machine), the others do nothing.  So each lane visits only its own
+    // last-type events of each gap, found through a per-block table, in LDS,
+    // of event-position bits per type hash.  A block with many prefix events
+    // is stepped event by event instead.  tm, evs: this wave's 64-entry LDS
+    // scratch.
+    template <bool NOTE>
+    __device__ void sparse(const int *ids, const int *ticks, int b, int e, const Cand<N> &c,
+                           const Prefix<N> &u, unsigned long long *tm, int2 *evs, int *status)
+    {
+        static_assert(N >= 2, "per-type dispatch needs a shared prefix");
+        b = uniform(b);
+        e = uniform(e);
+        if (b >= e) return;
+        const int lane = __lane_id();
+        const int dty = c.ty[N - 1];
+        const int dh = dty & 63;
+        int k = b + lane < e ? b + lane : e - 1;
+        int nid = ids[k], ntk = ticks[k];
+        for (int i = b; i < e; i += WAVE) {
+            const int id = nid, tk = ntk;
+            k = i + WAVE + lane < e ? i + WAVE + lane : e - 1;
+            nid = ids[k];
+            ntk = ticks[k];
+            const bool v = i + lane < e;
+            const int h = id & 63;
+            const unsigned long long pm = __ballot(v & (((u.mask >> h) & 1ull) != 0));
+            if (__popcll(pm) > 20) {
+                const int nv = e - i < WAVE ? e - i : WAVE;
+                for (int j = 0; j < nv; ++j) {
+                    const int ev = __builtin_amdgcn_readlane(id, j);
+                    const int t = __builtin_amdgcn_readlane(tk, j);
+                    complete(m.step_u(ev, t, c, u, status), i + j, t, NOTE);
+                }
+                continue;
+            }
+            tm[lane] = 0;
+            evs[lane] = make_int2(id, tk);
+            if (v) atomicOr(&tm[h], 1ull << lane);
+            unsigned long long ml = tm[dh] & ~pm;
+            unsigned long long rem = pm;
+            for (;;) {
+                const int x = rem ? (int)__builtin_ctzll(rem) : WAVE;
+                const unsigned long long below = x >= WAVE ? ~0ull : (1ull << x) - 1ull;
+                unsigned long long gp = ml & below;
+                ml &= ~below;
+                while (gp) {
+                    const int pos = (int)__builtin_ctzll(gp);
+                    gp &= gp - 1ull;
+                    const int2 et = evs[pos];
+                    if (et.x != dty) continue;
+                    if (m.step_last(et.x, et.y, c)) {
+                        m.reset();
+                        ++cnt;
+                        lastx = 0;
+                        if (NOTE) note(i + pos, et.y);
+                        gp = 0;
+                    } else if (!EXACT) {
+                        gp = 0;  // relaxed: a later tick cannot pass a test this one failed
+                    }
+                }
+                if (x >= WAVE) break;
+                const int ev = __builtin_amdgcn_readlane(id, x);
+                const int t = __builtin_amdgcn_readlane(tk, x);
+                complete(m.step_u(ev, t, c, u, status), i + x, t, NOTE);
+                rem &= rem - 1ull;
+            }
+        }
+    }
+
     // Look-back and tail of a segment: completions count only at idx >= L,
     // exit slots are numbered at idx >= lamn, look-back E_(N) events are
     // counted into ks.
@@ -582,6 +659,16 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map1(const int *__restrict__ ids_
     const bool uni = shared_prefix<N>(cd, o >= 0, u);
     MainRun<N, EXACT, D> r;
     r.m.reset();
+    if constexpr (N >= 2) {
+        __shared__ unsigned long long s_tm[WPB][WAVE];
+        __shared__ int2 s_ev[WPB][WAVE];
+        if (uni && g.sparse) {
+            const int wv = threadIdx.x >> 6;
+            r.template sparse<false>(ids_, ticks_, 0, g.n, cd, u, s_tm[wv], s_ev[wv], g.status);
+            if (o >= 0) g.out[o] = r.cnt;
+            return;
+        }
+    }
     if (uni)
         r.template body<true, false, true>((cptr)ids_, (cptr)ticks_, g.cmask, 0, g.n, cd, u,
                                            g.status);
