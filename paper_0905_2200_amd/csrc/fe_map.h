@@ -46,7 +46,8 @@
 namespace fe {
 
 typedef const __attribute__((address_space(4))) int *cptr;
-static constexpr int EMPTY = 0x7fffffff;
+static constexpr int EMPTY = 0x7fffffff;  // an unused window slot (after the live ones)
+static constexpr int GONE = -0x7fffffff - 1;  // end of a window dropped by a reset
 static constexpr int QREC = 4;  // slot-0 completions remembered for merging
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -128,12 +129,21 @@ template <int N> struct Relaxed {
 template <int N, int D> struct Exact {
     int wa[N > 1 ? N - 1 : 1][D];
     int wb[N > 1 ? N - 1 : 1][D];
+    __device__ __forceinline__ Exact()
+    {
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k)
+#pragma unroll
+            for (int d = 0; d < D; ++d) { wa[k][d] = EMPTY; wb[k][d] = GONE; }
+    }
+    // Empty lists: every window ends before any tick, so each is dropped as
+    // expired by the next push and no hop test passes.
     __device__ __forceinline__ void reset()
     {
 #pragma unroll
         for (int k = 0; k < N - 1; ++k)
 #pragma unroll
-            for (int d = 0; d < D; ++d) { wa[k][d] = EMPTY; wb[k][d] = EMPTY; }
+            for (int d = 0; d < D; ++d) wb[k][d] = GONE;
     }
     __device__ __forceinline__ bool hit(int k, int t) const
     {
@@ -337,9 +347,8 @@ template <int N, bool EXACT, int D> struct MainRun {
     // events there that passes the hop test completes (and empties the
     // machine), the others do nothing.  So each lane visits only its own
     // last-type events of each gap, found through a per-block table, in LDS,
-    // of event-position bits per type hash.  A block with many prefix events
-    // is stepped event by event instead.  tm, evs: this wave's 64-entry LDS
-    // scratch.
+    // of event-position bits per type hash.  tm, evs: this wave's 64-entry
+    // LDS scratch.
     template <bool NOTE>
     __device__ void sparse(const int *ids, const int *ticks, int b, int e, const Cand<N> &c,
                            const Prefix<N> &u, unsigned long long *tm, int2 *evs, int *status)
@@ -361,15 +370,6 @@ template <int N, bool EXACT, int D> struct MainRun {
             const bool v = i + lane < e;
             const int h = id & 63;
             const unsigned long long pm = __ballot(v & (((u.mask >> h) & 1ull) != 0));
-            if (__popcll(pm) > 20) {
-                const int nv = e - i < WAVE ? e - i : WAVE;
-                for (int j = 0; j < nv; ++j) {
-                    const int ev = __builtin_amdgcn_readlane(id, j);
-                    const int t = __builtin_amdgcn_readlane(tk, j);
-                    complete(m.step_u(ev, t, c, u, status), i + j, t, NOTE);
-                }
-                continue;
-            }
             tm[lane] = 0;
             evs[lane] = make_int2(id, tk);
             if (v) atomicOr(&tm[h], 1ull << lane);
@@ -380,26 +380,72 @@ template <int N, bool EXACT, int D> struct MainRun {
                 const unsigned long long below = x >= WAVE ? ~0ull : (1ull << x) - 1ull;
                 unsigned long long gp = ml & below;
                 ml &= ~below;
+                // the lane's last-type events before x: the first that passes
+                // the hop test completes (the test itself does not change state)
+                int cpos = -1, ct = 0;
                 while (gp) {
                     const int pos = (int)__builtin_ctzll(gp);
                     gp &= gp - 1ull;
                     const int2 et = evs[pos];
                     if (et.x != dty) continue;
                     if (m.step_last(et.x, et.y, c)) {
-                        m.reset();
-                        ++cnt;
-                        lastx = 0;
-                        if (NOTE) note(i + pos, et.y);
-                        gp = 0;
-                    } else if (!EXACT) {
-                        gp = 0;  // relaxed: a later tick cannot pass a test this one failed
+                        cpos = pos;
+                        ct = et.y;
+                        break;
                     }
+                    if (!EXACT) break;  // relaxed: a later tick cannot pass a test this one failed
+                }
+                if (cpos >= 0) {
+                    m.reset();
+                    ++cnt;
+                    lastx = 0;
+                    if (NOTE) note(i + cpos, ct);
                 }
                 if (x >= WAVE) break;
                 const int ev = __builtin_amdgcn_readlane(id, x);
                 const int t = __builtin_amdgcn_readlane(tk, x);
                 complete(m.step_u(ev, t, c, u, status), i + x, t, NOTE);
                 rem &= rem - 1ull;
+            }
+        }
+    }
+
+    // Per-type dispatch for a wave without a shared prefix: in each block of
+    // 64 events a lane visits, in stream order, only the events whose type
+    // hash is one of its own nodes' (the others leave its machine as it is).
+    // take: the lane takes part (padding lanes visit nothing).
+    template <bool NOTE>
+    __device__ void sparse_lane(const int *ids, const int *ticks, int b, int e, const Cand<N> &c,
+                                bool take, unsigned long long *tm, int2 *evs, int *status)
+    {
+        b = uniform(b);
+        e = uniform(e);
+        if (b >= e) return;
+        const int lane = __lane_id();
+        int k = b + lane < e ? b + lane : e - 1;
+        int nid = ids[k], ntk = ticks[k];
+        for (int i = b; i < e; i += WAVE) {
+            const int id = nid, tk = ntk;
+            k = i + WAVE + lane < e ? i + WAVE + lane : e - 1;
+            nid = ids[k];
+            ntk = ticks[k];
+            tm[lane] = 0;
+            evs[lane] = make_int2(id, tk);
+            if (i + lane < e) atomicOr(&tm[id & 63], 1ull << lane);
+            unsigned long long ml = 0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) ml |= tm[c.ty[q] & 63];
+            if (!take) ml = 0;
+            while (ml) {
+                const int pos = (int)__builtin_ctzll(ml);
+                ml &= ml - 1ull;
+                const int2 et = evs[pos];
+                if (m.step(et.x, et.y, c, true, status)) {
+                    m.reset();
+                    ++cnt;
+                    lastx = 0;
+                    if (NOTE) note(i + pos, et.y);
+                }
             }
         }
     }
@@ -644,8 +690,11 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map(const int *__restrict__ ids_,
 }
 
 // Whole-stream Map (P = 1, one machine per lane, no segment bookkeeping):
-// the launch used when the tiles alone fill the GPU.
-template <int N, bool EXACT, int D>
+// the launch used when the tiles alone fill the GPU.  SPARSE: per-type
+// dispatch (shared-prefix waves by gaps between prefix events, the others
+// lane by lane); otherwise every event goes through every lane, shared-prefix
+// waves skipping the 8-event chunks that hold no shared type.
+template <int N, bool EXACT, int D, bool SPARSE>
 __global__ __launch_bounds__(WAVE *WPB) void k_map1(const int *__restrict__ ids_,
                                                     const int *__restrict__ ticks_, MapGroup g)
 {
@@ -659,21 +708,29 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map1(const int *__restrict__ ids_
     const bool uni = shared_prefix<N>(cd, o >= 0, u);
     MainRun<N, EXACT, D> r;
     r.m.reset();
-    if constexpr (N >= 2) {
+    if constexpr (SPARSE) {
         __shared__ unsigned long long s_tm[WPB][WAVE];
         __shared__ int2 s_ev[WPB][WAVE];
-        if (uni && g.sparse) {
-            const int wv = threadIdx.x >> 6;
-            r.template sparse<false>(ids_, ticks_, 0, g.n, cd, u, s_tm[wv], s_ev[wv], g.status);
-            if (o >= 0) g.out[o] = r.cnt;
-            return;
+        const int wv = threadIdx.x >> 6;
+        bool done = false;
+        if constexpr (N >= 2) {
+            if (uni) {
+                r.template sparse<false>(ids_, ticks_, 0, g.n, cd, u, s_tm[wv], s_ev[wv],
+                                         g.status);
+                done = true;
+            }
         }
+        if (!done)
+            r.template sparse_lane<false>(ids_, ticks_, 0, g.n, cd, o >= 0, s_tm[wv], s_ev[wv],
+                                          g.status);
+    } else {
+        if (uni)
+            r.template body<true, false, true>((cptr)ids_, (cptr)ticks_, g.cmask, 0, g.n, cd, u,
+                                               g.status);
+        else
+            r.template body<false, false>((cptr)ids_, (cptr)ticks_, g.cmask, 0, g.n, cd, u,
+                                          g.status);
     }
-    if (uni)
-        r.template body<true, false, true>((cptr)ids_, (cptr)ticks_, g.cmask, 0, g.n, cd, u,
-                                           g.status);
-    else
-        r.template body<false, false>((cptr)ids_, (cptr)ticks_, g.cmask, 0, g.n, cd, u, g.status);
     if (o >= 0) g.out[o] = r.cnt;
 }
 
@@ -809,9 +866,14 @@ template <int N, bool EXACT, int D> void map_n(const MapGroup &g, hipStream_t s,
     if (fix) {
         hipLaunchKernelGGL((k_fixup<N, EXACT, D>), dim3((unsigned)((g.tiles + WPB - 1) / WPB)),
                            dim3(WAVE * WPB), 0, s, g.ids, g.ticks, g);
+    } else if (g.P == 1 && g.sparse) {
+        hipLaunchKernelGGL((k_map1<N, EXACT, D, true>),
+                           dim3((unsigned)((g.tiles + WPB - 1) / WPB)), dim3(WAVE * WPB), 0, s,
+                           g.ids, g.ticks, g);
     } else if (g.P == 1) {
-        hipLaunchKernelGGL((k_map1<N, EXACT, D>), dim3((unsigned)((g.tiles + WPB - 1) / WPB)),
-                           dim3(WAVE * WPB), 0, s, g.ids, g.ticks, g);
+        hipLaunchKernelGGL((k_map1<N, EXACT, D, false>),
+                           dim3((unsigned)((g.tiles + WPB - 1) / WPB)), dim3(WAVE * WPB), 0, s,
+                           g.ids, g.ticks, g);
     } else {
         const int64_t items = (int64_t)g.tiles * g.P;
         hipLaunchKernelGGL((k_map<N, EXACT, D>), dim3((unsigned)((items + WPB - 1) / WPB)),

@@ -1,0 +1,146 @@
+"""GPU parity of the per-type dispatch Map path (FE_PARAM_TYPE_DISPATCH):
+with it on and off, whole-stream counts (P = 1) equal the CPU oracle's bit for
+bit, for waves whose candidates share their first N-1 types (runs of 64 in
+input order) and for waves that do not; with type ids that collide in the
+64-entry type hash; with last types equal to a shared type; with blocks
+crowded with shared-type events; and on ragged and tiny streams."""
+import numpy as np
+import pytest
+
+from paper_0905_2200_amd import synth
+from tests.gpu_util import banner, have_gpu, oracle_counts
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not have_gpu(), reason="needs a GPU")]
+
+EXACT, RELAXED = 0, 1
+# all of depth class 2 (two list windows), so a candidate set stays one group
+IV_D2 = [(50, 100), (100, 200), (60, 110)]
+
+
+@pytest.fixture(scope="module")
+def fe():
+    from paper_0905_2200_amd import fe as fe_mod
+    return fe_mod
+
+
+@pytest.fixture(scope="module")
+def ctx(fe):
+    c = fe.Context(0)
+    yield c
+    c.close()
+
+
+def _count(ctx, fe, ids, ticks, num_types, cand, mode, dispatch):
+    ctx.set_param(fe.PARAM_SEGMENTS, 1)
+    ctx.set_param(fe.PARAM_TYPE_DISPATCH, dispatch)
+    try:
+        return ctx.count(ids, ticks, num_types, cand, mode).cpu().numpy()
+    finally:
+        ctx.set_param(fe.PARAM_SEGMENTS, 0)
+        ctx.set_param(fe.PARAM_TYPE_DISPATCH, 1)
+
+
+def _prefix_runs(rng, N, runs, prefixes, last_pool, ivs=IV_D2):
+    """runs x 64 candidates; run r shares the node types prefixes[r % len]
+    (N-1 of them); each lane draws its last type and intervals."""
+    eps = []
+    for r in range(runs):
+        pre = prefixes[r % len(prefixes)]
+        for _ in range(64):
+            last = int(rng.choice(last_pool))
+            iv = [ivs[int(rng.integers(len(ivs)))] for _ in range(N - 1)]
+            eps.append((tuple(pre) + (last,), tuple(a for a, _ in iv), tuple(b for _, b in iv)))
+    return synth.pack(eps)
+
+
+def _stream(rng, n, num_types, weights=None, mean_gap=8):
+    ids = rng.choice(num_types, size=n, p=weights).astype(np.int32)
+    ticks = np.cumsum(rng.integers(0, 2 * mean_gap + 1, size=n)).astype(np.int32)
+    return ids, ticks
+
+
+def _check(ctx, fe, ids_h, ticks_h, num_types, cand, what):
+    ids, ticks = ctx.stream_tensors(ids_h, ticks_h)
+    for mode in (RELAXED, EXACT):
+        want = oracle_counts(ids_h, ticks_h, num_types, cand, mode)
+        for dispatch in (1, 0):
+            got = _count(ctx, fe, ids, ticks, num_types, cand, mode, dispatch)
+            bad = np.nonzero(got != want)[0]
+            assert bad.size == 0, (what, mode, dispatch, bad[:5], got[bad[:5]], want[bad[:5]])
+        assert (want > 0).any(), what  # the case is not vacuous
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
+def test_shared_prefix_runs(ctx, fe, N):
+    rng = np.random.default_rng(100 + N)
+    ids_h, ticks_h = _stream(rng, 40_000, 16)
+    prefixes = [tuple(int(x) for x in rng.integers(0, 16, N - 1)) for _ in range(6)]
+    cand = _prefix_runs(rng, N, 12, prefixes, np.arange(16))
+    banner("shared-prefix runs: N=%d, %d candidates, n=%d" % (N, cand["M"], ids_h.size))
+    _check(ctx, fe, ids_h, ticks_h, 16, cand, "N=%d" % N)
+
+
+def test_type_hash_collisions(ctx, fe):
+    # types t, t+64, t+128 share a hash; prefixes and last types mix them,
+    # and some last types equal a shared type
+    rng = np.random.default_rng(7)
+    T = 200
+    w = np.full(T, 1.0)
+    for t in (5, 69, 133, 197, 9, 73):
+        w[t] = 40.0
+    ids_h, ticks_h = _stream(rng, 60_000, T, w / w.sum())
+    prefixes = [(5, 69, 133), (69, 5, 9), (133, 197, 73), (9, 9, 5)]
+    pool = np.array([5, 69, 133, 197, 9, 73, 137, 1, 65, 129])
+    cand = _prefix_runs(rng, 4, 8, prefixes, pool)
+    banner("hash collisions: %d candidates, n=%d" % (cand["M"], ids_h.size))
+    _check(ctx, fe, ids_h, ticks_h, T, cand, "collisions")
+
+
+def test_crowded_prefix_blocks(ctx, fe):
+    # most events carry a shared type: blocks are stepped event by event
+    rng = np.random.default_rng(11)
+    w = np.full(32, 1.0)
+    w[[3, 4, 5]] = 60.0
+    ids_h, ticks_h = _stream(rng, 30_000, 32, w / w.sum(), mean_gap=30)
+    cand = _prefix_runs(rng, 4, 6, [(3, 4, 5), (5, 3, 4)], np.arange(32))
+    banner("crowded prefix blocks: %d candidates" % cand["M"])
+    _check(ctx, fe, ids_h, ticks_h, 32, cand, "crowded")
+
+
+def test_mixed_waves_and_ragged_streams(ctx, fe):
+    # random candidates (no shared prefix: lane-by-lane dispatch) next to
+    # shared-prefix runs, over streams of every length class around a block
+    rng = np.random.default_rng(23)
+    eps = synth.random_episodes(rng, 700, 12, 4, IV_D2, n_min=1)
+    runs = _prefix_runs(rng, 4, 3, [(1, 2, 3)], np.arange(12))
+    eps += [(tuple(runs["types"][m, :4]), tuple(runs["lo"][m, :3]), tuple(runs["hi"][m, :3]))
+            for m in range(runs["M"])]
+    cand = synth.pack(eps)
+    for n in (1, 2, 63, 64, 65, 127, 129, 1000, 4097, 20_001):
+        ids_h, ticks_h = _stream(rng, n, 12, mean_gap=40)
+        ids, ticks = ctx.stream_tensors(ids_h, ticks_h)
+        banner("mixed waves: n=%d, %d candidates" % (n, cand["M"]))
+        for mode in (RELAXED, EXACT):
+            want = oracle_counts(ids_h, ticks_h, 12, cand, mode)
+            for dispatch in (1, 0):
+                got = _count(ctx, fe, ids, ticks, 12, cand, mode, dispatch)
+                bad = np.nonzero(got != want)[0]
+                assert bad.size == 0, (n, mode, dispatch, bad[:5], got[bad[:5]], want[bad[:5]])
+
+
+def test_mining_same_with_and_without_dispatch(ctx, fe):
+    s = synth.config_mining(duration_s=60.0)
+    banner("mining 60 s: n=%d theta=%d" % (s["ids"].size, s["theta"]))
+    ids, ticks = ctx.stream_tensors(s["ids"], s["ticks"])
+    res = {}
+    for dispatch in (1, 0):
+        ctx.set_param(fe.PARAM_TYPE_DISPATCH, dispatch)
+        try:
+            out = ctx.mine(ids, ticks, s["num_types"], s["intervals"], s["theta"], 5)
+        finally:
+            ctx.set_param(fe.PARAM_TYPE_DISPATCH, 1)
+        res[dispatch] = out
+    assert len(res[0]) == len(res[1])
+    for a, b in zip(res[0], res[1]):
+        for k in ("types", "lo", "hi", "upper", "exact"):
+            assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (a["level"], k)
