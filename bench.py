@@ -184,10 +184,14 @@ def main():
         log("level %d: candidates %d survivors %d frequent %d gen %.1f ms count %.1f ms" % (
             lv["level"], lv["n_candidates"], lv["n_survivors"], lv["n_frequent"],
             lv["gen_ms"], lv["count_ms"]))
+    host = {k: v for k, v in kst.items() if k.startswith("host_")}
+    kst = {k: v for k, v in kst.items() if not k.startswith("host_")}
     tot_kms = sum(v["total_ms"] for v in kst.values())
     for k, v in sorted(kst.items(), key=lambda kv: -kv[1]["total_ms"]):
         log("kernel %-24s launches %5d total %9.2f ms (%.1f%%) ee %.3e" % (
             k, v["launches"], v["total_ms"], 100 * v["total_ms"] / max(tot_kms, 1e-9), v["ee"]))
+    for k, v in sorted(host.items(), key=lambda kv: -kv[1]["total_ms"]):
+        log("host phase %-20s calls %5d total %9.2f ms" % (k[5:], v["launches"], v["total_ms"]))
 
     maps = {k: v for k, v in kst.items() if k.startswith("map_") and v["total_ms"] > 0}
     dom = max(maps.items(), key=lambda kv: kv[1]["total_ms"]) if maps else None

@@ -691,13 +691,93 @@ extern "C" int fe_count_two_pass(fe_ctx *c, const int32_t *ids, const int32_t *t
 
 namespace {
 
+// Large host arrays are written in full by the loops that fill them, so they
+// are allocated without value-initialisation.
+template <class T> struct NoInit : std::allocator<T> {
+    template <class U> struct rebind {
+        typedef NoInit<U> other;
+    };
+    NoInit() = default;
+    template <class U> NoInit(const NoInit<U> &) {}
+    template <class U> void construct(U *p) noexcept { ::new ((void *)p) U; }
+    template <class U, class... A> void construct(U *p, A &&...a)
+    {
+        ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+typedef std::vector<int, NoInit<int>> ivec;
+
+// Host worker threads for candidate generation and packing.
+int host_threads()
+{
+    static const int n = [] {
+        const unsigned h = std::thread::hardware_concurrency();
+        return (int)std::max(1u, std::min(16u, h ? h : 1u));
+    }();
+    return n;
+}
+
+// f(begin, end, part) over [0, n) split into contiguous parts, in parallel
+// when each part gets at least `grain` items.
+template <class F> int par_for(int64_t n, int64_t grain, F &&f)
+{
+    const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), n / grain));
+    if (parts <= 1) {
+        f((int64_t)0, n, 0);
+        return 1;
+    }
+    std::vector<std::thread> th;
+    th.reserve(parts);
+    for (int q = 0; q < parts; ++q)
+        th.emplace_back([&f, n, parts, q] { f(n * q / parts, n * (q + 1) / parts, q); });
+    for (auto &t : th) t.join();
+    return parts;
+}
+
+// Order-preserving parallel filter of [0, n): the indices i with keep(i).
+template <class P> void par_select(int64_t n, P &&keep, ivec &out)
+{
+    const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), n / 65536));
+    std::vector<int64_t> cnt(parts + 1, 0);
+    par_for(n, (n + parts - 1) / std::max(parts, 1), [&](int64_t b, int64_t e, int q) {
+        int64_t k = 0;
+        for (int64_t i = b; i < e; ++i) k += keep(i) ? 1 : 0;
+        cnt[q + 1] = k;
+    });
+    for (int q = 0; q < parts; ++q) cnt[q + 1] += cnt[q];
+    out.resize(cnt[parts]);
+    par_for(n, (n + parts - 1) / std::max(parts, 1), [&](int64_t b, int64_t e, int q) {
+        int64_t k = cnt[q];
+        for (int64_t i = b; i < e; ++i)
+            if (keep(i)) out[k++] = (int)i;
+    });
+}
+
+// Host phase timer: with FE_PARAM_TIMING on, adds the wall time of its scope
+// to the per-kind table under `name` (a host phase, no device work).
+struct HTimer {
+    fe_ctx *c;
+    const char *name;
+    double t0;
+    HTimer(fe_ctx *c_, const char *name_) : c(c_), name(name_), t0(now_ms()) {}
+    ~HTimer()
+    {
+        if (!c->param[FE_PARAM_TIMING]) return;
+        auto &g = c->kstats[name];
+        const double ms = now_ms() - t0;
+        g.launches++;
+        g.total_ms += ms;
+        g.max_ms = std::max(g.max_ms, ms);
+    }
+};
+
 // An episode of size m is keyed by its interleaved tuple
 // (E1, lo1, hi1, E2, ..., lo_(m-1), hi_(m-1), E_m): 3m-2 ints.  The prefix
 // (first m-1 nodes) is the first 3m-5 ints, the suffix (last m-1 nodes)
 // the last 3m-5 ints.
 struct Episodes {
-    int m = 0;             // episode size
-    std::vector<int> key;  // [count * (3m-2)]
+    int m = 0;   // episode size
+    ivec key;    // [count * (3m-2)]
     size_t count() const { return m ? key.size() / (3 * m - 2) : 0; }
     const int *at(size_t i) const { return key.data() + i * (3 * m - 2); }
 };
@@ -711,7 +791,7 @@ void sort_episodes(Episodes &E, std::vector<int> *vals_a, std::vector<int> *vals
     std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
         return std::lexicographical_compare(E.at(a), E.at(a) + w, E.at(b), E.at(b) + w);
     });
-    std::vector<int> k2(E.key.size());
+    ivec k2(E.key.size());
     std::vector<int> a2(vals_a ? F : 0), b2(vals_b ? F : 0);
     for (size_t i = 0; i < F; ++i) {
         std::memcpy(k2.data() + i * w, E.at(idx[i]), w * sizeof(int));
@@ -742,31 +822,52 @@ void gen_level2(const std::vector<int> &F1, const std::vector<int> &ilo,
 }
 
 // Level m+1 from the sorted frequent set of size m: alpha joined with every
-// beta whose first m-1 nodes and intervals equal alpha's last m-1.
+// beta whose first m-1 nodes and intervals equal alpha's last m-1, in the
+// order (alpha, beta).  Each alpha's betas are one contiguous range of F;
+// ranges are found and written in parallel.
 void gen_join(const Episodes &F, Episodes &out)
 {
-    const int m = F.m, w = 3 * m - 2, ov = 3 * m - 5;
+    const int m = F.m, w = 3 * m - 2, ov = 3 * m - 5, wo = w + 3;
     out.m = m + 1;
-    out.key.clear();
-    const size_t cnt = F.count();
-    std::vector<size_t> order(cnt);
-    for (size_t i = 0; i < cnt; ++i) order[i] = i;
-    auto pre_less = [&](size_t b, const int *key) {
-        return std::lexicographical_compare(F.at(b), F.at(b) + ov, key, key + ov);
-    };
-    auto key_less = [&](const int *key, size_t b) {
-        return std::lexicographical_compare(key, key + ov, F.at(b), F.at(b) + ov);
-    };
-    for (size_t a = 0; a < cnt; ++a) {
-        const int *suf = F.at(a) + 3;
-        auto lo_it = std::lower_bound(order.begin(), order.end(), suf, pre_less);
-        auto hi_it = std::upper_bound(lo_it, order.end(), suf, key_less);
-        for (auto it = lo_it; it != hi_it; ++it) {
-            const int *al = F.at(a), *be = F.at(*it);
-            out.key.insert(out.key.end(), al, al + 3);
-            out.key.insert(out.key.end(), be, be + w);
+    const int64_t cnt = (int64_t)F.count();
+    std::vector<int64_t> first(cnt), off(cnt + 1, 0);
+    par_for(cnt, 4096, [&](int64_t b, int64_t e, int) {
+        for (int64_t a = b; a < e; ++a) {
+            const int *suf = F.at(a) + 3;
+            int64_t lo = 0, hi = cnt;  // first beta whose prefix is >= suf
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (std::lexicographical_compare(F.at(mid), F.at(mid) + ov, suf, suf + ov))
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            int64_t l2 = lo, h2 = cnt;  // first beta whose prefix is > suf
+            while (l2 < h2) {
+                const int64_t mid = (l2 + h2) >> 1;
+                if (!std::lexicographical_compare(suf, suf + ov, F.at(mid), F.at(mid) + ov))
+                    l2 = mid + 1;
+                else
+                    h2 = mid;
+            }
+            first[a] = lo;
+            off[a + 1] = l2 - lo;
         }
-    }
+    });
+    for (int64_t a = 0; a < cnt; ++a) off[a + 1] += off[a];
+    out.key.resize((size_t)off[cnt] * wo);
+    par_for(cnt, 4096, [&](int64_t b, int64_t e, int) {
+        for (int64_t a = b; a < e; ++a) {
+            int *o = out.key.data() + (size_t)off[a] * wo;
+            const int *al = F.at(a);
+            for (int64_t j = 0; j < off[a + 1] - off[a]; ++j, o += wo) {
+                o[0] = al[0];
+                o[1] = al[1];
+                o[2] = al[2];
+                std::memcpy(o + 3, F.at(first[a] + j), w * sizeof(int));
+            }
+        }
+    });
 }
 
 struct LevelOut {
@@ -782,9 +883,9 @@ struct LevelOut {
 // of join siblings (same first m-1 types, consecutive in generation order)
 // fill whole tiles, so those waves take the shared-prefix path; a run's
 // remainder of at least half a tile gets a padded tile of its own, shorter
-// remainders are packed together.
+// remainders are packed together after every run's tiles.
 struct HostPack {
-    std::vector<int> rec, orig, tileW;
+    ivec rec, orig, tileW;
     std::vector<GroupDesc> groups;
     int tiles = 0;
 };
@@ -800,7 +901,9 @@ int host_dcls(const int *k, int m, bool exact)
     return bound <= 1 ? 0 : bound <= 2 ? 1 : bound <= 4 ? 2 : 3;
 }
 
-void host_pack(const Episodes &C, const std::vector<int> &order, bool exact, HostPack &hp)
+// order: the candidates to pack (indices into C), or null for all of C in
+// order; n: their number.
+void host_pack(const Episodes &C, const int *order, int64_t n, bool exact, HostPack &hp)
 {
     const int m = C.m;
     const int ri = rec_ints(m);
@@ -809,50 +912,75 @@ void host_pack(const Episodes &C, const std::vector<int> &order, bool exact, Hos
     hp.tileW.clear();
     hp.groups.clear();
     hp.tiles = 0;
-    std::vector<int> byc[NDCLS];
-    for (int i : order) byc[host_dcls(C.at(i), m, exact)].push_back(i);
+    auto cand = [&](int64_t i) { return order ? order[i] : (int)i; };
+    // depth classes, stable
+    ivec byc[NDCLS];
+    if (!exact) {
+        byc[0].resize(n);
+        par_for(n, 65536, [&](int64_t b, int64_t e, int) {
+            for (int64_t i = b; i < e; ++i) byc[0][i] = cand(i);
+        });
+    } else {
+        ivec cls(n);
+        par_for(n, 65536, [&](int64_t b, int64_t e, int) {
+            for (int64_t i = b; i < e; ++i) cls[i] = host_dcls(C.at(cand(i)), m, true);
+        });
+        for (int k = 0; k < NDCLS; ++k) {
+            ivec sel;
+            par_select(n, [&](int64_t i) { return cls[i] == k; }, sel);
+            byc[k].resize(sel.size());
+            par_for((int64_t)sel.size(), 65536, [&](int64_t b, int64_t e, int) {
+                for (int64_t i = b; i < e; ++i) byc[k][i] = cand(sel[i]);
+            });
+        }
+    }
     auto same_prefix = [&](int a, int b) {
         const int *x = C.at(a), *y = C.at(b);
         for (int j = 0; j < m - 1; ++j)
             if (x[3 * j] != y[3 * j]) return false;
         return true;
     };
-    std::vector<int> lanes;  // candidate per lane slot, -1 = padding
     for (int cls = 0; cls < NDCLS; ++cls) {
-        const std::vector<int> &v = byc[cls];
-        if (v.empty()) continue;
-        lanes.clear();
-        std::vector<int> mixed;
-        size_t i = 0;
-        while (i < v.size()) {
-            size_t j = i + 1;
-            while (j < v.size() && same_prefix(v[i], v[j])) ++j;
-            size_t r = j - i;
-            size_t q = i;
-            while (r >= (size_t)WAVE) {
-                lanes.insert(lanes.end(), v.begin() + q, v.begin() + q + WAVE);
-                q += WAVE;
-                r -= WAVE;
-            }
-            if (r >= (size_t)WAVE / 2) {
-                lanes.insert(lanes.end(), v.begin() + q, v.begin() + j);
-                lanes.insert(lanes.end(), WAVE - r, -1);
-            } else {
-                mixed.insert(mixed.end(), v.begin() + q, v.begin() + j);
-            }
-            i = j;
+        const ivec &v = byc[cls];
+        const int64_t V = (int64_t)v.size();
+        if (V == 0) continue;
+        // runs of equal first m-1 types
+        ivec starts;
+        par_select(V, [&](int64_t i) { return i == 0 || !same_prefix(v[i - 1], v[i]); }, starts);
+        const int64_t R = (int64_t)starts.size();
+        std::vector<int64_t> toff(R + 1, 0), moff(R + 1, 0);
+        for (int64_t r = 0; r < R; ++r) {
+            const int64_t len = (r + 1 < R ? starts[r + 1] : V) - starts[r];
+            const int64_t rem = len % WAVE;
+            toff[r + 1] = toff[r] + len / WAVE + (rem >= WAVE / 2 ? 1 : 0);
+            moff[r + 1] = moff[r] + (rem >= WAVE / 2 ? 0 : rem);
         }
-        lanes.insert(lanes.end(), mixed.begin(), mixed.end());
-        if (lanes.size() % WAVE) lanes.insert(lanes.end(), WAVE - lanes.size() % WAVE, -1);
-        const int tiles = (int)(lanes.size() / WAVE);
-        GroupDesc gd{(m - 1) * NDCLS + cls, tiles, hp.tiles, (int64_t)hp.rec.size(), 0,
-                     (int64_t)v.size()};
+        const int64_t run_tiles = toff[R], nmixed = moff[R];
+        const int tiles = (int)(run_tiles + (nmixed + WAVE - 1) / WAVE);
+        ivec lanes((size_t)tiles * WAVE);
+        par_for(R, 1024, [&](int64_t b, int64_t e, int) {
+            for (int64_t r = b; r < e; ++r) {
+                const int64_t s0 = starts[r], len = (r + 1 < R ? starts[r + 1] : V) - s0;
+                const int64_t full = len / WAVE * WAVE, rem = len - full;
+                int *dst = lanes.data() + toff[r] * WAVE;
+                std::memcpy(dst, v.data() + s0, full * sizeof(int));
+                if (rem >= WAVE / 2) {
+                    std::memcpy(dst + full, v.data() + s0 + full, rem * sizeof(int));
+                    std::fill(dst + full + rem, dst + full + WAVE, -1);
+                } else {
+                    std::memcpy(lanes.data() + run_tiles * WAVE + moff[r], v.data() + s0 + full,
+                                rem * sizeof(int));
+                }
+            }
+        });
+        std::fill(lanes.begin() + run_tiles * WAVE + nmixed, lanes.end(), -1);
+        GroupDesc gd{(m - 1) * NDCLS + cls, tiles, hp.tiles, (int64_t)hp.rec.size(), 0, V};
         const size_t rec0 = hp.rec.size(), orig0 = hp.orig.size(), tw0 = hp.tileW.size();
         hp.rec.resize(rec0 + (size_t)tiles * ri);
         hp.orig.resize(orig0 + (size_t)tiles * WAVE);
         hp.tileW.resize(tw0 + tiles);
-        auto fill_tiles = [&](int t0, int t1) {
-            for (int t = t0; t < t1; ++t) {
+        par_for(tiles, 256, [&](int64_t t0, int64_t t1, int) {
+            for (int64_t t = t0; t < t1; ++t) {
                 int *rec = hp.rec.data() + rec0 + (size_t)t * ri;
                 int W = 0;
                 for (int l = 0; l < WAVE; ++l) {
@@ -878,17 +1006,7 @@ void host_pack(const Episodes &C, const std::vector<int> &order, bool exact, Hos
                 }
                 hp.tileW[tw0 + t] = W;
             }
-        };
-        const int nth = (int)std::min<int64_t>(16, std::max<int64_t>(1, tiles / 2048));
-        if (nth <= 1) {
-            fill_tiles(0, tiles);
-        } else {
-            std::vector<std::thread> th;
-            for (int q = 0; q < nth; ++q)
-                th.emplace_back(fill_tiles, (int)((int64_t)tiles * q / nth),
-                                (int)((int64_t)tiles * (q + 1) / nth));
-            for (auto &t : th) t.join();
-        }
+        });
         for (int t = 0; t < tiles; ++t) gd.wmax = std::max(gd.wmax, hp.tileW[tw0 + t]);
         hp.tiles += tiles;
         hp.groups.push_back(gd);
@@ -976,8 +1094,11 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
     for (int level = 2; level <= max_level && F.count() > 0 && n_iv > 0; ++level) {
         t0 = now_ms();
         Episodes C;
-        if (level == 2) gen_level2(levels[0].types, ilo, ihi, C);
-        else gen_join(F, C);
+        {
+            HTimer ht(c, "host_gen");
+            if (level == 2) gen_level2(levels[0].types, ilo, ihi, C);
+            else gen_join(F, C);
+        }
         const size_t M = C.count();
         if (M == 0) break;
         if (M >= (size_t)1 << 31 || M * level >= (size_t)1 << 31)
@@ -990,25 +1111,37 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         if ((rc = ensure(c, c->mn, 4 * sizeof(int)))) return rc;
         int *up = P<int>(c->mup), *ex = P<int>(c->mex);
         // pass 1 (Algorithm 3) over every candidate
-        std::vector<int> order(M);
-        for (size_t i = 0; i < M; ++i) order[i] = (int)i;
         HostPack hp;
-        host_pack(C, order, false, hp);
-        if ((rc = upload_pack(c, hp))) return rc;
+        {
+            HTimer ht(c, "host_pack");
+            host_pack(C, nullptr, (int64_t)M, false, hp);
+        }
+        {
+            HTimer ht(c, "host_upload");
+            if ((rc = upload_pack(c, hp))) return rc;
+        }
         if ((rc = launch_groups(c, ids, ticks, si, hp.groups, false, up))) return rc;
         // elimination (Algorithm 4): survivors have upper >= theta
-        std::vector<int> uph(M);
-        HIPCHK(c, hipMemcpyAsync(uph.data(), up, M * sizeof(int), hipMemcpyDeviceToHost, s));
+        ivec uph(M), order;
         HIPCHK(c, hipStreamSynchronize(s));
-        order.clear();
-        for (size_t i = 0; i < M; ++i)
-            if (uph[i] >= theta) order.push_back((int)i);
+        {
+            HTimer ht(c, "host_select");
+            HIPCHK(c, hipMemcpyAsync(uph.data(), up, M * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            par_select((int64_t)M, [&](int64_t i) { return uph[i] >= theta; }, order);
+        }
         const int64_t nsurv = (int64_t)order.size();
         // pass 2 (Algorithm 1) over the survivors; the others keep -1
         launch_fill(ex, -1, (int64_t)M, s);
         if (nsurv > 0) {
-            host_pack(C, order, true, hp);
-            if ((rc = upload_pack(c, hp))) return rc;
+            {
+                HTimer ht(c, "host_pack");
+                host_pack(C, order.data(), nsurv, true, hp);
+            }
+            {
+                HTimer ht(c, "host_upload");
+                if ((rc = upload_pack(c, hp))) return rc;
+            }
             if ((rc = launch_groups(c, ids, ticks, si, hp.groups, true, ex))) return rc;
         }
         // frequent = exact >= theta
@@ -1408,10 +1541,8 @@ extern "C" int fe_batch_create(fe_ctx *c, int32_t R, const fe_job *jobs, fe_batc
                 back.push_back(m);
             }
             if (back.empty()) continue;
-            std::vector<int> order(back.size());
-            for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
             HostPack hp;
-            host_pack(C, order, true, hp);
+            host_pack(C, nullptr, (int64_t)back.size(), true, hp);
             for (const GroupDesc &gd : hp.groups) {
                 fe_batch::Group g{r, gd.key, b->ntiles + gd.tile_base, gd.tiles, gd.wmax};
                 b->groups.push_back(g);
@@ -1972,10 +2103,8 @@ extern "C" int fe_server_create(fe_ctx *c, const fe_server_config *cfg, const in
             back.push_back(m);
         }
         if (back.empty()) continue;
-        std::vector<int> order(back.size());
-        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
         HostPack hp;
-        host_pack(C, order, true, hp);
+        host_pack(C, nullptr, (int64_t)back.size(), true, hp);
         for (GroupDesc gd : hp.groups) {
             gd.tile_base += sv->ntiles;
             gd.rec_base += (int64_t)rec.size();
