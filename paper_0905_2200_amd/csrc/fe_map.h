@@ -124,6 +124,18 @@ template <int N> struct Relaxed {
             return comp;
         }
     }
+    // Nodes 0..N-2 of a shared-prefix wave only (the last node's test is
+    // taken elsewhere); lanes with on = false leave their lists as they are.
+    __device__ __forceinline__ void push_u(int e, int t, const Cand<N> &c, const Prefix<N> &u,
+                                           bool on, int *)
+    {
+        if constexpr (N > 1) {
+#pragma unroll
+            for (int i = N - 2; i >= 1; --i)
+                if (e == u.ty[i]) dl[i] = (on & (t <= dl[i - 1])) ? t + c.hi[i] : dl[i];
+            if (e == u.ty[0]) dl[0] = on ? t + c.hi[0] : dl[0];
+        }
+    }
 };
 
 template <int N, int D> struct Exact {
@@ -219,6 +231,20 @@ template <int N, int D> struct Exact {
                 if (e == u.ty[0]) push(0, t, c.lo[0], c.hi[0], status);
             }
             return comp;
+        }
+    }
+    // Nodes 0..N-2 of a shared-prefix wave only (the last node's test is
+    // taken elsewhere); lanes with on = false leave their lists as they are.
+    __device__ __forceinline__ void push_u(int e, int t, const Cand<N> &c, const Prefix<N> &u,
+                                           bool on, int *status)
+    {
+        if constexpr (N > 1) {
+#pragma unroll
+            for (int i = N - 2; i >= 1; --i)
+                if (e == u.ty[i])
+                    if (on && hit(i - 1, t)) push(i, t, c.lo[i], c.hi[i], status);
+            if (e == u.ty[0])
+                if (on) push(0, t, c.lo[0], c.hi[0], status);
         }
     }
 };
@@ -340,15 +366,19 @@ template <int N, bool EXACT, int D> struct MainRun {
     // Bulk of a segment for a shared-prefix wave by per-type dispatch (the
     // paper's CPU counter keeps, per event type, the machines waiting on it;
     // this is the wave form of that idea).  Events come in blocks of 64, one
-    // per lane (vector loads).  "Prefix events" -- those whose type hash is
-    // that of a shared node -- form a wave-uniform set and are stepped by the
-    // whole wave in stream order.  Between two prefix events a lane's lists
-    // change only through its own last node: the first of its last-type
-    // events there that passes the hop test completes (and empties the
-    // machine), the others do nothing.  So each lane visits only its own
-    // last-type events of each gap, found through a per-block table, in LDS,
-    // of event-position bits per type hash.  tm, evs: this wave's 64-entry
-    // LDS scratch.
+    // per lane (vector loads), and each block is written to LDS with a table
+    // of event-position bits per type hash.  "Prefix events" (type hash of a
+    // shared node) are stepped by the whole wave in stream order; of the
+    // others a lane visits only those of its own last type.
+    //   Only prefix events of node N-2's type change list N-2, the one the
+    // last node tests, and so split the block into spans ending at such an
+    // event (or at the block end).  Within a span the first last-type event
+    // of a lane that passes the test -- prefix events included, the span's
+    // closing one too, as completions come before pushes -- completes and
+    // empties the machine; only one can, as list N-2 then stays empty to the
+    // span's end.  Then the span's prefix events push in order, except, in
+    // that lane, those at or before its completion.  tm, evs: this wave's
+    // 64-entry LDS scratch.
     template <bool NOTE>
     __device__ void sparse(const int *ids, const int *ticks, int b, int e, const Cand<N> &c,
                            const Prefix<N> &u, unsigned long long *tm, int2 *evs, int *status)
@@ -360,6 +390,7 @@ template <int N, bool EXACT, int D> struct MainRun {
         const int lane = __lane_id();
         const int dty = c.ty[N - 1];
         const int dh = dty & 63;
+        const int bh = u.ty[N - 2] & 63;
         int k = b + lane < e ? b + lane : e - 1;
         int nid = ids[k], ntk = ticks[k];
         for (int i = b; i < e; i += WAVE) {
@@ -370,18 +401,18 @@ template <int N, bool EXACT, int D> struct MainRun {
             const bool v = i + lane < e;
             const int h = id & 63;
             const unsigned long long pm = __ballot(v & (((u.mask >> h) & 1ull) != 0));
+            const unsigned long long bm = __ballot(v & (h == bh));
             tm[lane] = 0;
             evs[lane] = make_int2(id, tk);
             if (v) atomicOr(&tm[h], 1ull << lane);
-            unsigned long long ml = tm[dh] & ~pm;
-            unsigned long long rem = pm;
+            unsigned long long ml = tm[dh];
+            unsigned long long remp = pm, remb = bm;
             for (;;) {
-                const int x = rem ? (int)__builtin_ctzll(rem) : WAVE;
-                const unsigned long long below = x >= WAVE ? ~0ull : (1ull << x) - 1ull;
-                unsigned long long gp = ml & below;
-                ml &= ~below;
-                // the lane's last-type events before x: the first that passes
-                // the hop test completes (the test itself does not change state)
+                const bool last = remb == 0;
+                const int xb = last ? WAVE - 1 : (int)__builtin_ctzll(remb);
+                const unsigned long long upto = xb >= WAVE - 1 ? ~0ull : (2ull << xb) - 1ull;
+                unsigned long long gp = ml & upto;
+                ml &= ~upto;
                 int cpos = -1, ct = 0;
                 while (gp) {
                     const int pos = (int)__builtin_ctzll(gp);
@@ -401,11 +432,17 @@ template <int N, bool EXACT, int D> struct MainRun {
                     lastx = 0;
                     if (NOTE) note(i + cpos, ct);
                 }
-                if (x >= WAVE) break;
-                const int ev = __builtin_amdgcn_readlane(id, x);
-                const int t = __builtin_amdgcn_readlane(tk, x);
-                complete(m.step_u(ev, t, c, u, status), i + x, t, NOTE);
-                rem &= rem - 1ull;
+                unsigned long long pp = remp & upto;
+                remp &= ~upto;
+                while (pp) {
+                    const int x = (int)__builtin_ctzll(pp);
+                    pp &= pp - 1ull;
+                    const int ev = __builtin_amdgcn_readlane(id, x);
+                    const int t = __builtin_amdgcn_readlane(tk, x);
+                    m.push_u(ev, t, c, u, x > cpos, status);
+                }
+                if (last) break;
+                remb &= remb - 1ull;
             }
         }
     }
