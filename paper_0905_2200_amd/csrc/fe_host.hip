@@ -1427,6 +1427,7 @@ int batch_plan(fe_batch *b)
         d.lam = P<int>(b->lamd);
         d.tbl = P<int2>(b->tbld);
         d.status = P<int>(c->status);
+        d.sparse = c->param[FE_PARAM_TYPE_DISPATCH] != 0;
         const int q0 = q;
         int nq = 1;
         for (int dd = 0; dd < NDCLS; ++dd) nq += L.n_ex[dd] > 0;
@@ -1895,6 +1896,7 @@ int server_launch(fe_server *sv, fe_server::Lane &ln)
     d.lam = (int *)(ar + o_lam);
     d.tbl = (int2 *)(ar + o_tbl);
     d.status = P<int>(c->status);
+    d.sparse = c->param[FE_PARAM_TYPE_DISPATCH] != 0;
     int *lists_d = (int *)(ar + o_lists);
     int *fr = (int *)(ar + o_fr), *fx = (int *)(ar + o_fx), *qc = (int *)(ar + o_q);
     const int grid = std::max(1, sv->ncu * sv->cfg.waves_per_cu / WPB);

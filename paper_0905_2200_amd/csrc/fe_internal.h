@@ -79,6 +79,7 @@ struct BatchDev {
     int2 *tbl;
     int *flags;
     int *status;
+    int sparse;  // per-type dispatch for the bulk of each item
 };
 
 // launchers (fe_kernels.hip)

@@ -43,6 +43,8 @@
 
 #include "fe_internal.h"
 
+#include <type_traits>
+
 namespace fe {
 
 typedef const __attribute__((address_space(4))) int *cptr;
@@ -644,11 +646,14 @@ struct ItemArgs {
     int *out;        // counts, indexed by the candidate's input index
     int *status;
     const unsigned long long *cmask;  // per aligned 8-event chunk type masks, or null
+    const int *gids, *gticks;         // the same stream for vector loads
+    unsigned long long *tm;           // this wave's LDS scratch (per-type dispatch)
+    int2 *evs;
 };
 
 // Map step of one work item.  o: the lane's candidate index (-1 = padding);
 // valid: the lane's candidate takes part (its result is written).
-template <int N, bool EXACT, int D>
+template <int N, bool EXACT, int D, bool SPARSE>
 __device__ __forceinline__ void map_item(const ItemArgs &a, int o, bool valid)
 {
     Cand<N> cd;
@@ -658,9 +663,28 @@ __device__ __forceinline__ void map_item(const ItemArgs &a, int o, bool valid)
 
     MainRun<N, EXACT, D> r;
     r.m.reset();
+    // bulk [b, e) of the segment, NOTE: remember slot-0 completions
+    auto bulk = [&](auto note_tag, int b, int e) {
+        constexpr bool NOTE = decltype(note_tag)::value;
+        if constexpr (SPARSE) {
+            bool done = false;
+            if constexpr (N >= 2) {
+                if (uni) {
+                    r.template sparse<NOTE>(a.gids, a.gticks, b, e, cd, u, a.tm, a.evs, a.status);
+                    done = true;
+                }
+            }
+            if (!done)
+                r.template sparse_lane<NOTE>(a.gids, a.gticks, b, e, cd, valid, a.tm, a.evs,
+                                             a.status);
+        } else if (uni) {
+            r.template body<true, NOTE>(a.ids, a.ticks, a.cmask, b, e, cd, u, a.status);
+        } else {
+            r.template body<false, NOTE>(a.ids, a.ticks, a.cmask, b, e, cd, u, a.status);
+        }
+    };
     if (a.P == 1) {
-        if (uni) r.template body<true, false>(a.ids, a.ticks, a.cmask, 0, a.n, cd, u, a.status);
-        else r.template body<false, false>(a.ids, a.ticks, a.cmask, 0, a.n, cd, u, a.status);
+        bulk(std::false_type(), 0, a.n);
         if (valid) a.out[o] = r.cnt;
         return;
     }
@@ -676,8 +700,7 @@ __device__ __forceinline__ void map_item(const ItemArgs &a, int o, bool valid)
     // slot 0: the last completion before L lies before lam
     for (int k = 0; k < QREC; ++k) { r.ci[k] = -1; r.ck[k] = 0; r.ct[k] = 0; }
     r.edge(a.ids, a.ticks, lam, L, L, lamn, cd, a.status);
-    if (uni) r.template body<true, true>(a.ids, a.ticks, a.cmask, L, xl, cd, u, a.status);
-    else r.template body<false, true>(a.ids, a.ticks, a.cmask, L, xl, cd, u, a.status);
+    bulk(std::true_type(), L, xl);
     r.edge(a.ids, a.ticks, xl, R, L, lamn, cd, a.status);
     if (valid) a.tb[0] = make_int2(r.cnt, r.lastx < KMAX ? r.lastx : KMAX - 1);
 
@@ -699,7 +722,7 @@ __device__ __forceinline__ void map_item(const ItemArgs &a, int o, bool valid)
     }
 }
 
-template <int N, bool EXACT, int D>
+template <int N, bool EXACT, int D, bool SPARSE>
 __global__ __launch_bounds__(WAVE *WPB) void k_map(const int *__restrict__ ids_,
                                                    const int *__restrict__ ticks_, MapGroup g)
 {
@@ -723,7 +746,13 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map(const int *__restrict__ ids_,
     a.out = g.out;
     a.status = g.status;
     a.cmask = g.cmask;
-    map_item<N, EXACT, D>(a, o, o >= 0);
+    __shared__ unsigned long long s_tm[WPB][WAVE];
+    __shared__ int2 s_ev[WPB][WAVE];
+    a.gids = ids_;
+    a.gticks = ticks_;
+    a.tm = s_tm[threadIdx.x >> 6];
+    a.evs = s_ev[threadIdx.x >> 6];
+    map_item<N, EXACT, D, SPARSE>(a, o, o >= 0);
 }
 
 // Whole-stream Map (P = 1, one machine per lane, no segment bookkeeping):
@@ -775,9 +804,11 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map1(const int *__restrict__ ids_
 // items of many recordings from a queue (heaviest first) until it is empty.
 // In the exact pass only candidates that survived the relaxed pass count;
 // the others get -1.
-template <int N, bool EXACT, int D>
+template <int N, bool EXACT, int D, bool SPARSE>
 __global__ __launch_bounds__(WAVE *WPB) void k_persist(BatchDev b)
 {
+    __shared__ unsigned long long s_tm[WPB][WAVE];
+    __shared__ int2 s_ev[WPB][WAVE];
     const int lane = __lane_id();
     for (;;) {
         int it = 0;
@@ -809,7 +840,11 @@ __global__ __launch_bounds__(WAVE *WPB) void k_persist(BatchDev b)
         a.out = out;
         a.status = b.status;
         a.cmask = nullptr;
-        map_item<N, EXACT, D>(a, o, valid);
+        a.gids = jb.ids;
+        a.gticks = jb.ticks;
+        a.tm = s_tm[threadIdx.x >> 6];
+        a.evs = s_ev[threadIdx.x >> 6];
+        map_item<N, EXACT, D, SPARSE>(a, o, valid);
     }
 }
 
@@ -881,7 +916,12 @@ void persist_n(const BatchDev &b, int grid, const int *ctiles, int nct, hipStrea
             hipLaunchKernelGGL((k_persist_fixup<N, EXACT, D>), dim3((nct + WPB - 1) / WPB),
                                dim3(WAVE * WPB), 0, s, b, ctiles, nct);
     } else {
-        hipLaunchKernelGGL((k_persist<N, EXACT, D>), dim3(grid), dim3(WAVE * WPB), 0, s, b);
+        if (b.sparse)
+            hipLaunchKernelGGL((k_persist<N, EXACT, D, true>), dim3(grid), dim3(WAVE * WPB), 0,
+                               s, b);
+        else
+            hipLaunchKernelGGL((k_persist<N, EXACT, D, false>), dim3(grid), dim3(WAVE * WPB), 0,
+                               s, b);
     }
 }
 
@@ -913,8 +953,14 @@ template <int N, bool EXACT, int D> void map_n(const MapGroup &g, hipStream_t s,
                            g.ids, g.ticks, g);
     } else {
         const int64_t items = (int64_t)g.tiles * g.P;
-        hipLaunchKernelGGL((k_map<N, EXACT, D>), dim3((unsigned)((items + WPB - 1) / WPB)),
-                           dim3(WAVE * WPB), 0, s, g.ids, g.ticks, g);
+        if (g.sparse)
+            hipLaunchKernelGGL((k_map<N, EXACT, D, true>),
+                               dim3((unsigned)((items + WPB - 1) / WPB)), dim3(WAVE * WPB), 0, s,
+                               g.ids, g.ticks, g);
+        else
+            hipLaunchKernelGGL((k_map<N, EXACT, D, false>),
+                               dim3((unsigned)((items + WPB - 1) / WPB)), dim3(WAVE * WPB), 0, s,
+                               g.ids, g.ticks, g);
     }
 }
 
