@@ -86,10 +86,14 @@ typedef enum fe_param {
                                  0 = per-candidate sequential walk             */
     FE_PARAM_TIMING = 4,     /* 1 = time every kernel launch with HIP events on
                                 the context's stream (fe_get_kernel_stats)     */
-    FE_PARAM_TYPE_DISPATCH = 5 /* 1 (default) = waves whose candidates share
-                                their first N-1 types step only the events of
-                                those types, plus each lane its own last-type
-                                events; 0 = every event through every lane    */
+    FE_PARAM_TYPE_DISPATCH = 5 /* 1 (default) = per-type dispatch: a lane steps
+                                only the events of its own episode's types
+                                (for waves whose candidates share their first
+                                N-1 types, those events wave-wide plus each
+                                lane's own last-type events); 0 = every event
+                                through every lane.  Read at each count call,
+                                at fe_batch_create and at each server round.
+                                Counts are identical either way.              */
 } fe_param;
 
 typedef struct fe_ctx fe_ctx;
