@@ -132,6 +132,27 @@ int fe_count(fe_ctx *ctx, const int32_t *ids, const int32_t *ticks, int64_t n,
              const int32_t *lo, const int32_t *hi, int32_t M, int32_t nmax,
              int mode, int32_t *counts_out);
 
+/* Incremental counting of a growing recording, processed in consecutive
+ * partitions (the paper's real-time "chip-on-chip" use, Sec. 1 and Sec. 7).
+ * ids/ticks[0, n) on the device are the stream so far; the events before
+ * `from` must be the ones earlier calls saw (append-only).  count_io and
+ * last_io (device int32[M], in candidate order) carry, per candidate, the
+ * completions counted in [0, from) and the index of the last of them (-1 if
+ * none); on return they cover [0, n).  Start with 0 / -1 / from = 0, then
+ * call with from = the previous n after each append.  The counts equal
+ * fe_count over [0, n) in the same mode.  Why it is exact: after a
+ * completion the machine is empty, and no occurrence spans more than
+ * W = sum(hi) ticks, so from `from` on the machine acts like a fresh one
+ * started after max(last, lam-1), lam = first index with tick >= t_from - W
+ * (the argument behind the segment stitching of fe_count); only that much
+ * is read again before `from`.  Errors: FE_EINVAL for from outside [0, n],
+ * null carry arrays or bad candidates (as fe_count); stream errors as
+ * fe_validate.  Synchronises once (candidate grouping). */
+int fe_count_resume(fe_ctx *ctx, const int32_t *ids, const int32_t *ticks, int64_t n,
+                    int32_t num_types, const int32_t *types, const int32_t *len,
+                    const int32_t *lo, const int32_t *hi, int32_t M, int32_t nmax,
+                    int mode, int64_t from, int32_t *count_io, int32_t *last_io);
+
 /* Two-pass elimination, Algorithm 4 (Sec. 5.3.2): upper_out[m] = relaxed
  * count; candidates with upper < theta are dropped (exact_out[m] = -1);
  * exact_out[m] = exact count for the others.  *n_survivors_out (device

@@ -255,9 +255,19 @@ struct GroupDesc {
     int64_t ncand;
 };
 
-// Map (+ plan, Concatenate, fix-up when segmented) for every packed group.
+// Incremental count (fe_count_resume): events before `from` were counted by
+// earlier calls; per candidate, count_io / last_io carry the count and the
+// index of the last completion so far.
+struct Resume {
+    int from;
+    int *count_io, *last_io;
+};
+
+// Map (+ plan, Concatenate, fix-up when segmented) for every packed group;
+// with rs, the incremental whole-stream Map instead.
 int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si,
-                  const std::vector<GroupDesc> &groups, bool exact, int *out)
+                  const std::vector<GroupDesc> &groups, bool exact, int *out,
+                  const Resume *rs = nullptr)
 {
     hipStream_t s = c->stream;
     int rc;
@@ -285,9 +295,18 @@ int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo 
         g.lam = nullptr;
         g.tbl = nullptr;
         g.flags = nullptr;
-        g.P = choose_P(c, tiles, si, gd.wmax);
+        g.P = rs ? 1 : choose_P(c, tiles, si, gd.wmax);
         g.sparse = c->param[FE_PARAM_TYPE_DISPATCH] != 0;
         c->stats.map_launches++;
+        if (rs) {
+            char rname[40];
+            snprintf(rname, sizeof rname, "resume_%s_n%d_d%d", exact ? "exact" : "relaxed", N,
+                     exact ? dcls_depth(dcls) : 1);
+            KTimer kt(c, rname, (double)gd.ncand * (double)(si.n - rs->from));
+            launch_resume(N, exact, dcls, g, rs->from, rs->count_io, rs->last_io, s);
+            HIPCHK(c, hipGetLastError());
+            continue;
+        }
         char kname[40];
         snprintf(kname, sizeof kname, "map_%s_n%d_d%d", exact ? "exact" : "relaxed", N,
                  exact ? dcls_depth(dcls) : 1);
@@ -333,7 +352,8 @@ int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo 
 // One counting pass (relaxed or exact) over candidates cin (optionally the
 // subset sel[0..*nsel) of them), writing out[m] for every counted m.
 int run_pass(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, int num_types,
-             const CandIn &cin, const int *sel, const int *nsel, int M, bool exact, int *out)
+             const CandIn &cin, const int *sel, const int *nsel, int M, bool exact, int *out,
+             const Resume *rs = nullptr)
 {
     hipStream_t s = c->stream;
     int rc;
@@ -397,8 +417,7 @@ int run_pass(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, 
         if (cnt[k])
             groups.push_back(GroupDesc{k, (cnt[k] + WAVE - 1) / WAVE, lay.tile_base[k],
                                        (int64_t)lay.rec_base[k], wmax[k], (int64_t)cnt[k]});
-    return launch_groups(c, ids, ticks, si, groups, exact, out);
-    return FE_OK;
+    return launch_groups(c, ids, ticks, si, groups, exact, out, rs);
 }
 
 int check_common(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int64_t n,
@@ -683,6 +702,32 @@ extern "C" int fe_count_two_pass(fe_ctx *c, const int32_t *ids, const int32_t *t
     CandIn cin{types, len, lo, hi, nmax};
     rc = two_pass_impl(c, ids, ticks, si, num_types, cin, M, theta, upper_out, exact_out,
                        n_survivors_out);
+    c->stats.last_call_ms = now_ms() - t0;
+    return rc;
+}
+
+extern "C" int fe_count_resume(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int64_t n,
+                               int32_t num_types, const int32_t *types, const int32_t *len,
+                               const int32_t *lo, const int32_t *hi, int32_t M, int32_t nmax,
+                               int mode, int64_t from, int32_t *count_io, int32_t *last_io)
+{
+    int rc;
+    const double t0 = now_ms();
+    if ((rc = check_common(c, ids, ticks, n, num_types))) return rc;
+    if ((rc = check_cands(c, types, len, lo, hi, M, nmax))) return rc;
+    if (mode != FE_EXACT && mode != FE_RELAXED) return fail(c, FE_EINVAL, "bad mode");
+    if (from < 0 || from > n) return fail(c, FE_EINVAL, "from outside [0, n]");
+    if (M > 0 && (!count_io || !last_io)) return fail(c, FE_EINVAL, "null carry arrays");
+    HIPCHK(c, hipSetDevice(c->device));
+    c->stats = fe_stats{};
+    StreamInfo si;
+    if ((rc = stream_info(c, ids, ticks, (int)n, num_types, si))) return rc;
+    if (M > 0 && from < n) {
+        CandIn cin{types, len, lo, hi, nmax};
+        const Resume rs{(int)from, count_io, last_io};
+        rc = run_pass(c, ids, ticks, si, num_types, cin, nullptr, nullptr, M, mode == FE_EXACT,
+                      nullptr, &rs);
+    }
     c->stats.last_call_ms = now_ms() - t0;
     return rc;
 }

@@ -268,6 +268,30 @@ static void pdispatch(int N, bool exact, int dcls, const BatchDev &b, int grid, 
     }
 }
 
+void launch_resume_n1(bool, int, const MapGroup &, int, int *, int *, hipStream_t);
+void launch_resume_n2(bool, int, const MapGroup &, int, int *, int *, hipStream_t);
+void launch_resume_n3(bool, int, const MapGroup &, int, int *, int *, hipStream_t);
+void launch_resume_n4(bool, int, const MapGroup &, int, int *, int *, hipStream_t);
+void launch_resume_n5(bool, int, const MapGroup &, int, int *, int *, hipStream_t);
+void launch_resume_n6(bool, int, const MapGroup &, int, int *, int *, hipStream_t);
+void launch_resume_n7(bool, int, const MapGroup &, int, int *, int *, hipStream_t);
+void launch_resume_n8(bool, int, const MapGroup &, int, int *, int *, hipStream_t);
+
+void launch_resume(int N, bool exact, int dcls, const MapGroup &g, int from, int *count_io,
+                   int *last_io, hipStream_t s)
+{
+    switch (N) {
+    case 1: return launch_resume_n1(exact, dcls, g, from, count_io, last_io, s);
+    case 2: return launch_resume_n2(exact, dcls, g, from, count_io, last_io, s);
+    case 3: return launch_resume_n3(exact, dcls, g, from, count_io, last_io, s);
+    case 4: return launch_resume_n4(exact, dcls, g, from, count_io, last_io, s);
+    case 5: return launch_resume_n5(exact, dcls, g, from, count_io, last_io, s);
+    case 6: return launch_resume_n6(exact, dcls, g, from, count_io, last_io, s);
+    case 7: return launch_resume_n7(exact, dcls, g, from, count_io, last_io, s);
+    default: return launch_resume_n8(exact, dcls, g, from, count_io, last_io, s);
+    }
+}
+
 void launch_persist(int N, bool exact, int dcls, const BatchDev &b, int grid, hipStream_t s)
 {
     pdispatch(N, exact, dcls, b, grid, nullptr, 0, s, false);

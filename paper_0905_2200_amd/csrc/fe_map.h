@@ -285,6 +285,7 @@ template <int N, bool EXACT, int D> struct MainRun {
     int ks = 0;     // E_(N) events in the look-back [lam, L)
     int q = 0;      // completions seen; the first QREC are kept for merging
     int ci[QREC], ck[QREC], ct[QREC];  // index, count after it, tick
+    int lastc = -1; // index of the last completion counted (whole-stream runs)
 
     __device__ __forceinline__ void note(int idx, int t)
     {
@@ -306,6 +307,7 @@ template <int N, bool EXACT, int D> struct MainRun {
                 m.reset();
                 ++cnt;
                 lastx = 0;
+                lastc = idx;
                 if (note_it) note(idx, t);
             }
         }
@@ -432,6 +434,7 @@ template <int N, bool EXACT, int D> struct MainRun {
                     m.reset();
                     ++cnt;
                     lastx = 0;
+                    lastc = i + cpos;
                     if (NOTE) note(i + cpos, ct);
                 }
                 unsigned long long pp = remp & upto;
@@ -483,6 +486,7 @@ template <int N, bool EXACT, int D> struct MainRun {
                     m.reset();
                     ++cnt;
                     lastx = 0;
+                    lastc = i + pos;
                     if (NOTE) note(i + pos, et.y);
                 }
             }
@@ -800,6 +804,95 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map1(const int *__restrict__ ids_
     if (o >= 0) g.out[o] = r.cnt;
 }
 
+// Incremental whole-stream Map: events [0, from) were counted by earlier
+// calls, which left each candidate's count and last completion index r in
+// count_io / last_io.  After a completion the machine is empty, and no
+// occurrence spans more than W = sum(hi) ticks, so from `from` on the true
+// machine behaves like a fresh one started after max(r, lam-1), lam being the
+// first index with tick >= t_from - W; nor can that fresh machine complete
+// before `from`.  Each lane runs such a machine from its own start (wave
+// head: per-lane gate; then the shared bulk) and adds what it counts.
+template <int N, bool EXACT, int D, bool SPARSE>
+__global__ __launch_bounds__(WAVE *WPB) void k_resume(const int *__restrict__ ids_,
+                                                      const int *__restrict__ ticks_, MapGroup g,
+                                                      int from, int *count_io, int *last_io)
+{
+    const int lane = __lane_id();
+    const int tile = uniform(blockIdx.x * WPB + (threadIdx.x >> 6));
+    if (tile >= g.tiles) return;
+    const int n = g.n;
+    const int o = g.orig[tile * WAVE + lane];
+    const bool valid = o >= 0;
+    Cand<N> cd;
+    load_cand<N>(cd, g.pk + (int64_t)tile * rec_ints(N), lane);
+    Prefix<N> u;
+    const bool uni = shared_prefix<N>(cd, valid, u);
+    int st = n;  // this lane's first event
+    int prev = -1;
+    if (valid) {
+        int W = 0;
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) W += cd.hi[k];
+        const int x = ticks_[from] - W;
+        int a = 0, b = from;
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if (ticks_[mid] < x) a = mid + 1;
+            else b = mid;
+        }
+        prev = last_io[o];
+        const int r1 = prev + 1 < 0 ? 0 : (prev + 1 > from ? from : prev + 1);
+        st = r1 > a ? r1 : a;
+    }
+    int smin = st, smax = valid ? st : 0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int x1 = __shfl_xor(smin, off), x2 = __shfl_xor(smax, off);
+        smin = x1 < smin ? x1 : smin;
+        smax = x2 > smax ? x2 : smax;
+    }
+    smin = uniform(smin);
+    smax = uniform(smax);
+    if (smin >= n) return;
+    MainRun<N, EXACT, D> r;
+    r.m.reset();
+    for_events<Unroll<N, EXACT, D>::U>((cptr)ids_, (cptr)ticks_, smin, smax,
+                                       [&](int ev, int t, int idx) {
+                                           if (r.m.step(ev, t, cd, valid & (idx >= st), g.status)) {
+                                               r.m.reset();
+                                               ++r.cnt;
+                                               r.lastc = idx;
+                                           }
+                                       });
+    if constexpr (SPARSE) {
+        __shared__ unsigned long long s_tm[WPB][WAVE];
+        __shared__ int2 s_ev[WPB][WAVE];
+        const int wv = threadIdx.x >> 6;
+        bool done = false;
+        if constexpr (N >= 2) {
+            if (uni) {
+                r.template sparse<false>(ids_, ticks_, smax, n, cd, u, s_tm[wv], s_ev[wv],
+                                         g.status);
+                done = true;
+            }
+        }
+        if (!done)
+            r.template sparse_lane<false>(ids_, ticks_, smax, n, cd, valid, s_tm[wv], s_ev[wv],
+                                          g.status);
+    } else {
+        if (uni)
+            r.template body<true, false>((cptr)ids_, (cptr)ticks_, nullptr, smax, n, cd, u,
+                                         g.status);
+        else
+            r.template body<false, false>((cptr)ids_, (cptr)ticks_, nullptr, smax, n, cd, u,
+                                          g.status);
+    }
+    if (valid) {
+        count_io[o] += r.cnt;
+        last_io[o] = r.lastc >= 0 ? r.lastc : prev;
+    }
+}
+
 // Persistent batched Map: a grid sized to the machine pops (tile, segment)
 // items of many recordings from a queue (heaviest first) until it is empty.
 // In the exact pass only candidates that survived the relaxed pass count;
@@ -961,6 +1054,31 @@ template <int N, bool EXACT, int D> void map_n(const MapGroup &g, hipStream_t s,
             hipLaunchKernelGGL((k_map<N, EXACT, D, false>),
                                dim3((unsigned)((items + WPB - 1) / WPB)), dim3(WAVE * WPB), 0, s,
                                g.ids, g.ticks, g);
+    }
+}
+
+template <int N, bool EXACT, int D>
+void resume_n(const MapGroup &g, int from, int *count_io, int *last_io, hipStream_t s)
+{
+    const dim3 grid((unsigned)((g.tiles + WPB - 1) / WPB)), block(WAVE * WPB);
+    if (g.sparse)
+        hipLaunchKernelGGL((k_resume<N, EXACT, D, true>), grid, block, 0, s, g.ids, g.ticks, g,
+                           from, count_io, last_io);
+    else
+        hipLaunchKernelGGL((k_resume<N, EXACT, D, false>), grid, block, 0, s, g.ids, g.ticks, g,
+                           from, count_io, last_io);
+}
+
+template <int N>
+void resume_dispatch_n(bool exact, int dcls, const MapGroup &g, int from, int *count_io,
+                       int *last_io, hipStream_t s)
+{
+    if (!exact) return resume_n<N, false, 1>(g, from, count_io, last_io, s);
+    switch (dcls) {
+    case 0: return resume_n<N, true, 1>(g, from, count_io, last_io, s);
+    case 1: return resume_n<N, true, 2>(g, from, count_io, last_io, s);
+    case 2: return resume_n<N, true, 4>(g, from, count_io, last_io, s);
+    default: return resume_n<N, true, 8>(g, from, count_io, last_io, s);
     }
 }
 

@@ -11,4 +11,9 @@ void launch_persist_n5(bool exact, int dcls, const BatchDev &b, int grid, const 
 {
     persist_dispatch_n<5>(exact, dcls, b, grid, ctiles, nct, s, fix);
 }
+void launch_resume_n5(bool exact, int dcls, const MapGroup &g, int from, int *count_io,
+                      int *last_io, hipStream_t s)
+{
+    resume_dispatch_n<5>(exact, dcls, g, from, count_io, last_io, s);
+}
 }  // namespace fe

@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "FE_OK", 1: "FE_EINVAL", 2: "FE_ENOMEM", 3: "FE_EDEVICE",
                 4: "FE_EUNSORTED", 5: "FE_ERANGE", 6: "FE_EBUSY", 7: "FE_EINTERNAL"}
 
 EXPORTS = ["fe_create", "fe_destroy", "fe_last_error", "fe_sync", "fe_set_param",
-           "fe_get_param", "fe_validate", "fe_count", "fe_count_two_pass", "fe_mine",
+           "fe_get_param", "fe_validate", "fe_count", "fe_count_resume", "fe_count_two_pass",
+           "fe_mine",
            "fe_result_free", "fe_get_stats", "fe_get_kernel_stats", "fe_reset_kernel_stats",
            "fe_batch_create", "fe_batch_run", "fe_batch_autotune", "fe_batch_set_tuning",
            "fe_batch_get_tuning", "fe_batch_destroy", "fe_count_batched",
@@ -125,6 +126,8 @@ def lib():
         "fe_count": ([CTX, V, V, I64, I32, V, V, V, V, I32, I32, ctypes.c_int, V], ctypes.c_int),
         "fe_count_two_pass": ([CTX, V, V, I64, I32, V, V, V, V, I32, I32, I32, V, V, V],
                               ctypes.c_int),
+        "fe_count_resume": ([CTX, V, V, I64, I32, V, V, V, V, I32, I32, ctypes.c_int, I64, V, V],
+                            ctypes.c_int),
         "fe_mine": ([CTX, V, V, I64, I32, V, V, I32, I32, I32, ctypes.POINTER(ctypes.POINTER(_Result))],
                     ctypes.c_int),
         "fe_result_free": ([ctypes.POINTER(_Result)], None),
@@ -294,6 +297,19 @@ class Context:
                             M, c["nmax"], int(mode), _ptr(out))
         self._check(rc)
         return out[:M]
+
+    def count_resume(self, ids, ticks, num_types, cand, mode, start, count_io, last_io):
+        """Incremental count (fe_count_resume): ids/ticks hold the stream so far,
+        events before `start` were counted by earlier calls; count_io / last_io
+        (device int32[M]) carry counts and last completion indices and are
+        updated in place."""
+        c = cand if "nmax" in cand and hasattr(cand["types"], "data_ptr") else self.cand_tensors(cand)
+        rc = self._call(lib().fe_count_resume, self.h, _ptr(ids), _ptr(ticks), ids.numel(),
+                        int(num_types), _ptr(c["types"]), _ptr(c["len"]), _ptr(c["lo"]),
+                        _ptr(c["hi"]), c["M"], c["nmax"], int(mode), int(start), _ptr(count_io),
+                        _ptr(last_io))
+        self._check(rc)
+        return count_io, last_io
 
     def count_two_pass(self, ids, ticks, num_types, cand, theta, upper=None, exact=None,
                        nsurv=None):
