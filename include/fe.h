@@ -86,7 +86,7 @@ typedef enum fe_param {
                                  0 = per-candidate sequential walk             */
     FE_PARAM_TIMING = 4,     /* 1 = time every kernel launch with HIP events on
                                 the context's stream (fe_get_kernel_stats)     */
-    FE_PARAM_TYPE_DISPATCH = 5 /* 1 (default) = per-type dispatch: a lane steps
+    FE_PARAM_TYPE_DISPATCH = 5, /* 1 (default) = per-type dispatch: a lane steps
                                 only the events of its own episode's types
                                 (for waves whose candidates share their first
                                 N-1 types, those events wave-wide plus each
@@ -94,6 +94,13 @@ typedef enum fe_param {
                                 through every lane.  Read at each count call,
                                 at fe_batch_create and at each server round.
                                 Counts are identical either way.              */
+    FE_PARAM_CROSSOVER_A = 6, /* hybrid rule (Algorithm 2, Eq. 2): a group of  */
+    FE_PARAM_CROSSOVER_B = 7  /* tiles >= A/N + B tiles of N-node candidates is
+                                counted whole-stream (P = 1), a smaller one by
+                                MapConcatenate with P >= 2.  Defaults 24200 and
+                                6926: fitted to crossovers measured on a 256-CU
+                                MI355X (python -m paper_0905_2200_amd.crossover).
+                                Ignored when FE_PARAM_SEGMENTS > 0.           */
 } fe_param;
 
 typedef struct fe_ctx fe_ctx;

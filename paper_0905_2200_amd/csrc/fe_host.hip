@@ -44,7 +44,7 @@ struct fe_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
-    int64_t param[6] = {0, 4096, 1024, 1, 0, 1};
+    int64_t param[8] = {0, 4096, 1024, 1, 0, 1, 24200, 6926};
     fe_stats stats{};
     // workspace
     Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
@@ -225,16 +225,24 @@ struct StreamInfo {
     int span;  // ticks[n-1] - ticks[0] + 1
 };
 
-// Segment count P for a group of `tiles` tiles: enough waves to fill the
-// GPU, but segments long against the look-back (about n*W/span events).
-int choose_P(const fe_ctx *c, int tiles, const StreamInfo &si, int Wmax)
+// Segment count P for a group of `tiles` tiles of N-node candidates: the
+// hybrid rule of Algorithm 2 (Eq. 2).  The whole-stream Map (the paper's
+// PTPE, P = 1) once the tiles reach the crossover C(N) = a/N + b tiles,
+// else MapConcatenate with P >= 2 segments, enough for the target number of
+// waves, each segment long against the look-back (about n*W/span events).
+// a and b were fitted to measured crossovers on a 256-CU MI355X
+// (paper_0905_2200_amd/crossover.py), the paper's Table 1 and a/N + b fit.
+int choose_P(const fe_ctx *c, int tiles, const StreamInfo &si, int Wmax, int N)
 {
     const int n = si.n;
     if (n <= 1) return 1;
     if (c->param[FE_PARAM_SEGMENTS] > 0)
         return (int)std::min<int64_t>(c->param[FE_PARAM_SEGMENTS], n);
+    const double cross = (double)c->param[FE_PARAM_CROSSOVER_A] / std::max(N, 1) +
+                         (double)c->param[FE_PARAM_CROSSOVER_B];
+    if ((double)tiles >= cross) return 1;
     const int64_t target = c->param[FE_PARAM_TARGET_WAVES];
-    int64_t P = (target + tiles - 1) / std::max(tiles, 1);
+    int64_t P = std::max<int64_t>(2, (target + tiles - 1) / std::max(tiles, 1));
     const double lb = (double)n * (double)Wmax / std::max(si.span, 1);
     const int64_t minseg = std::max<int64_t>(c->param[FE_PARAM_MIN_SEG_EVENTS],
                                              (int64_t)(8.0 * lb) + 64);
@@ -295,7 +303,7 @@ int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo 
         g.lam = nullptr;
         g.tbl = nullptr;
         g.flags = nullptr;
-        g.P = rs ? 1 : choose_P(c, tiles, si, gd.wmax);
+        g.P = rs ? 1 : choose_P(c, tiles, si, gd.wmax, N);
         g.sparse = c->param[FE_PARAM_TYPE_DISPATCH] != 0;
         c->stats.map_launches++;
         if (rs) {
@@ -600,7 +608,7 @@ extern "C" int fe_sync(fe_ctx *c)
 extern "C" int fe_set_param(fe_ctx *c, int param, int64_t value)
 {
     if (!c) return FE_EINVAL;
-    if (param < 0 || param > 5 || value < 0) return fail(c, FE_EINVAL, "bad parameter");
+    if (param < 0 || param > 7 || value < 0) return fail(c, FE_EINVAL, "bad parameter");
     if (param == FE_PARAM_TARGET_WAVES && value == 0) return fail(c, FE_EINVAL, "bad parameter");
     c->param[param] = value;
     return FE_OK;
@@ -608,7 +616,7 @@ extern "C" int fe_set_param(fe_ctx *c, int param, int64_t value)
 
 extern "C" int fe_get_param(const fe_ctx *c, int param, int64_t *value)
 {
-    if (!c || !value || param < 0 || param > 5) return FE_EINVAL;
+    if (!c || !value || param < 0 || param > 7) return FE_EINVAL;
     *value = c->param[param];
     return FE_OK;
 }

@@ -13,7 +13,7 @@ from tests.gpu_util import banner, have_gpu, oracle_counts
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not have_gpu(), reason="needs a GPU")]
 
 EXACT, RELAXED = 0, 1
-# all of depth class 2 (two list windows), so a candidate set stays one group
+# list depths 2, 2 and 3 (exact machines with 2 and 4 windows)
 IV_D2 = [(50, 100), (100, 200), (60, 110)]
 
 
@@ -144,3 +144,32 @@ def test_mining_same_with_and_without_dispatch(ctx, fe):
     for a, b in zip(res[0], res[1]):
         for k in ("types", "lo", "hi", "upper", "exact"):
             assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (a["level"], k)
+
+
+def test_hybrid_crossover_rule(ctx, fe):
+    # below the crossover C(N) = A/N + B tiles the count is segmented (P >= 2),
+    # at or above it whole-stream (P = 1); the counts are the same
+    rng = np.random.default_rng(41)
+    ids_h, ticks_h = _stream(rng, 50_000, 16)
+    # 40 tiles in one group (one list-depth class)
+    cand = _prefix_runs(rng, 4, 40, [(1, 2, 3), (4, 5, 6)], np.arange(16),
+                        ivs=[(50, 100), (100, 200)])
+    ids, ticks = ctx.stream_tensors(ids_h, ticks_h)
+    A0, B0 = ctx.get_param(fe.PARAM_CROSSOVER_A), ctx.get_param(fe.PARAM_CROSSOVER_B)
+    assert A0 / 4 + B0 > 40
+    want = oracle_counts(ids_h, ticks_h, 16, cand, EXACT)
+    try:
+        got = ctx.count(ids, ticks, 16, cand, EXACT).cpu().numpy()
+        assert ctx.stats()["segments_max"] >= 2
+        assert (got == want).all()
+        ctx.set_param(fe.PARAM_CROSSOVER_A, 0)
+        ctx.set_param(fe.PARAM_CROSSOVER_B, 40)   # C(4) = 40 tiles: whole stream
+        got = ctx.count(ids, ticks, 16, cand, EXACT).cpu().numpy()
+        assert ctx.stats()["segments_max"] == 1
+        assert (got == want).all()
+        ctx.set_param(fe.PARAM_CROSSOVER_B, 41)
+        ctx.count(ids, ticks, 16, cand, EXACT)
+        assert ctx.stats()["segments_max"] >= 2
+    finally:
+        ctx.set_param(fe.PARAM_CROSSOVER_A, A0)
+        ctx.set_param(fe.PARAM_CROSSOVER_B, B0)
