@@ -412,23 +412,30 @@ template <int N, bool EXACT, int D> struct MainRun {
             unsigned long long ml = tm[dh];
             unsigned long long remp = pm, remb = bm;
             for (;;) {
-                const bool last = remb == 0;
-                const int xb = last ? WAVE - 1 : (int)__builtin_ctzll(remb);
-                const unsigned long long upto = xb >= WAVE - 1 ? ~0ull : (2ull << xb) - 1ull;
+                // span: positions up to the lowest closing event (all if none)
+                const unsigned long long rb1 = remb - 1ull;
+                const unsigned long long upto = remb ? (remb ^ rb1) : ~0ull;
                 unsigned long long gp = ml & upto;
                 ml &= ~upto;
                 int cpos = -1, ct = 0;
-                while (gp) {
-                    const int pos = (int)__builtin_ctzll(gp);
-                    gp &= gp - 1ull;
-                    const int2 et = evs[pos];
-                    if (et.x != dty) continue;
-                    if (m.step_last(et.x, et.y, c)) {
-                        cpos = pos;
-                        ct = et.y;
-                        break;
+                if (gp) {
+                    int pos = (int)__builtin_ctzll(gp);
+                    int2 et = evs[pos];
+                    for (;;) {
+                        if (et.x == dty) {
+                            if (m.step_last(et.x, et.y, c)) {
+                                cpos = pos;
+                                ct = et.y;
+                                break;
+                            }
+                            // relaxed: a later tick cannot pass a test this one failed
+                            if (!EXACT) break;
+                        }
+                        gp &= gp - 1ull;
+                        if (!gp) break;
+                        pos = (int)__builtin_ctzll(gp);
+                        et = evs[pos];
                     }
-                    if (!EXACT) break;  // relaxed: a later tick cannot pass a test this one failed
                 }
                 if (cpos >= 0) {
                     m.reset();
@@ -446,8 +453,8 @@ template <int N, bool EXACT, int D> struct MainRun {
                     const int t = __builtin_amdgcn_readlane(tk, x);
                     m.push_u(ev, t, c, u, x > cpos, status);
                 }
-                if (last) break;
-                remb &= remb - 1ull;
+                if (!remb) break;
+                remb &= rb1;
             }
         }
     }
