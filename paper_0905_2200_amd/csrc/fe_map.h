@@ -169,6 +169,31 @@ template <int N, int D> struct Exact {
     __device__ __forceinline__ void push(int k, int t, int lo, int hi, int *status)
     {
         const int a = t + lo + 1, b = t + hi;
+        if constexpr (D == 1) {
+            // one live window at most: start anew, extend, or (invariant) fail
+            const bool gone = (wb[k][0] < t) | (wb[k][0] == EMPTY);
+            const bool mrg = !gone & (wb[k][0] >= a - 1);
+            if (!gone & !mrg) atomicOr(status, ST_INTERNAL);
+            wa[k][0] = mrg ? wa[k][0] : a;
+            wb[k][0] = b;
+            return;
+        } else if constexpr (D == 2) {
+            // drop window 0 if it ended before t (window 1 then moves down;
+            // window 1 cannot end before t while window 0 lives), then
+            // extend the last live window or append after it
+            const bool x0 = wb[k][0] < t;
+            const int c0a = x0 ? wa[k][1] : wa[k][0], c0b = x0 ? wb[k][1] : wb[k][0];
+            const int c1a = x0 ? EMPTY : wa[k][1], c1b = x0 ? EMPTY : wb[k][1];
+            const bool gone = (c0b < t) | (c0b == EMPTY);  // no live window left
+            const bool two = !gone & (c1b != EMPTY);
+            const bool mrg = two ? (c1b >= a - 1) : (!gone & (c0b >= a - 1));
+            if (two & !mrg) atomicOr(status, ST_INTERNAL);
+            wa[k][0] = gone ? a : c0a;
+            wb[k][0] = gone ? b : ((!two & mrg) ? b : c0b);
+            wa[k][1] = gone ? EMPTY : (two ? c1a : (mrg ? EMPTY : a));
+            wb[k][1] = gone ? EMPTY : (two ? (mrg ? b : c1b) : (mrg ? EMPTY : b));
+            return;
+        }
         int nd = 0;
 #pragma unroll
         for (int d = 0; d < D; ++d) nd += wb[k][d] < t ? 1 : 0;
