@@ -54,6 +54,27 @@ static constexpr int QREC = 4;  // slot-0 completions remembered for merging
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Per-type dispatch reads the stream 64 events per vector load through
+// buffer resources, whose range check returns 0 past the end (the prefetch
+// of the block after the last one), with the block offset in an SGPR.  A
+// resource covers at most EV_CHUNK events, so byte offsets stay below 2^31.
+static constexpr int EV_CHUNK = 1 << 28;
+static constexpr int BUF_DW3 = 0x00020000;  // raw 32-bit buffer access (gfx9)
+struct EvBuf {
+    __amdgpu_buffer_rsrc_t ri, rt;
+    __device__ __forceinline__ EvBuf(const int *ids, const int *ticks, int cb, int ce)
+        : ri(__builtin_amdgcn_make_buffer_rsrc((void *)(ids + cb), 0, (ce - cb) * 4, BUF_DW3)),
+          rt(__builtin_amdgcn_make_buffer_rsrc((void *)(ticks + cb), 0, (ce - cb) * 4, BUF_DW3))
+    {
+    }
+    // event rel + lane of the chunk (0 past its end)
+    __device__ __forceinline__ void load(int rel, int lane4, int &id, int &tk) const
+    {
+        id = __builtin_amdgcn_raw_buffer_load_b32(ri, lane4, rel * 4, 0);
+        tk = __builtin_amdgcn_raw_buffer_load_b32(rt, lane4, rel * 4, 0);
+    }
+};
+
 template <int N> struct Cand {
     int ty[N];
     int lo[N > 1 ? N - 1 : 1];
@@ -327,7 +348,7 @@ template <int N, bool EXACT, int D> struct MainRun {
     // completion.  UNI: the tile shares the types of nodes 0..N-2.
     __device__ __forceinline__ void complete(bool comp, int idx, int t, bool note_it)
     {
-        if (__builtin_expect(__ballot(comp) != 0, 0)) {
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(comp) != 0, 0)) {
             if (comp) {
                 m.reset();
                 ++cnt;
@@ -420,17 +441,20 @@ template <int N, bool EXACT, int D> struct MainRun {
         const int dty = c.ty[N - 1];
         const int dh = dty & 63;
         const int bh = u.ty[N - 2] & 63;
-        int k = b + lane < e ? b + lane : e - 1;
-        int nid = ids[k], ntk = ticks[k];
-        for (int i = b; i < e; i += WAVE) {
+        const int lane4 = lane * 4;
+        for (int cb = b; cb < e; cb += EV_CHUNK) {
+        const int ce = e - cb > EV_CHUNK ? cb + EV_CHUNK : e;
+        const EvBuf eb(ids, ticks, cb, ce);
+        int nid, ntk;
+        eb.load(0, lane4, nid, ntk);
+        for (int i = cb; i < ce; i += WAVE) {
             const int id = nid, tk = ntk;
-            k = i + WAVE + lane < e ? i + WAVE + lane : e - 1;
-            nid = ids[k];
-            ntk = ticks[k];
-            const bool v = i + lane < e;
+            eb.load(i - cb + WAVE, lane4, nid, ntk);
+            const bool v = lane < ce - i;
             const int h = id & 63;
-            const unsigned long long pm = __ballot(v & (((u.mask >> h) & 1ull) != 0));
-            const unsigned long long bm = __ballot(v & (h == bh));
+            const unsigned long long pm =
+                __builtin_amdgcn_ballot_w64(v & (((u.mask >> h) & 1ull) != 0));
+            const unsigned long long bm = __builtin_amdgcn_ballot_w64(v & (h == bh));
             tm[lane] = 0;
             evs[lane] = make_int2(id, tk);
             if (v) atomicOr(&tm[h], 1ull << lane);
@@ -482,6 +506,7 @@ template <int N, bool EXACT, int D> struct MainRun {
                 remb &= rb1;
             }
         }
+        }
     }
 
     // Per-type dispatch for a wave without a shared prefix: in each block of
@@ -496,16 +521,18 @@ template <int N, bool EXACT, int D> struct MainRun {
         e = uniform(e);
         if (b >= e) return;
         const int lane = __lane_id();
-        int k = b + lane < e ? b + lane : e - 1;
-        int nid = ids[k], ntk = ticks[k];
-        for (int i = b; i < e; i += WAVE) {
+        const int lane4 = lane * 4;
+        for (int cb = b; cb < e; cb += EV_CHUNK) {
+        const int ce = e - cb > EV_CHUNK ? cb + EV_CHUNK : e;
+        const EvBuf eb(ids, ticks, cb, ce);
+        int nid, ntk;
+        eb.load(0, lane4, nid, ntk);
+        for (int i = cb; i < ce; i += WAVE) {
             const int id = nid, tk = ntk;
-            k = i + WAVE + lane < e ? i + WAVE + lane : e - 1;
-            nid = ids[k];
-            ntk = ticks[k];
+            eb.load(i - cb + WAVE, lane4, nid, ntk);
             tm[lane] = 0;
             evs[lane] = make_int2(id, tk);
-            if (i + lane < e) atomicOr(&tm[id & 63], 1ull << lane);
+            if (lane < ce - i) atomicOr(&tm[id & 63], 1ull << lane);
             unsigned long long ml = 0;
 #pragma unroll
             for (int q = 0; q < N; ++q) ml |= tm[c.ty[q] & 63];
@@ -522,6 +549,7 @@ template <int N, bool EXACT, int D> struct MainRun {
                     if (NOTE) note(i + pos, et.y);
                 }
             }
+        }
         }
     }
 
