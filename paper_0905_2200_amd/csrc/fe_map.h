@@ -155,8 +155,9 @@ template <int N> struct Relaxed {
         if constexpr (N > 1) {
 #pragma unroll
             for (int i = N - 2; i >= 1; --i)
-                if (e == u.ty[i]) dl[i] = (on & (t <= dl[i - 1])) ? t + c.hi[i] : dl[i];
-            if (e == u.ty[0]) dl[0] = on ? t + c.hi[0] : dl[0];
+                if (__builtin_expect(e == u.ty[i], 0))
+                    dl[i] = (on & (t <= dl[i - 1])) ? t + c.hi[i] : dl[i];
+            if (__builtin_expect(e == u.ty[0], 0)) dl[0] = on ? t + c.hi[0] : dl[0];
         }
     }
 };
