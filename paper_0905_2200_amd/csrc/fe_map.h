@@ -208,7 +208,8 @@ template <int N, int D> struct Exact {
             const int c1a = x0 ? EMPTY : wa[k][1], c1b = x0 ? EMPTY : wb[k][1];
             const bool gone = (c0b < t) | (c0b == EMPTY);  // no live window left
             const bool two = !gone & (c1b != EMPTY);
-            const bool mrg = two ? (c1b >= a - 1) : (!gone & (c0b >= a - 1));
+            // (lane masks combined bitwise: no divergent control flow)
+            const bool mrg = (two & (c1b >= a - 1)) | (!two & !gone & (c0b >= a - 1));
             if (two & !mrg) atomicOr(status, ST_INTERNAL);
             wa[k][0] = gone ? a : c0a;
             wb[k][0] = gone ? b : ((!two & mrg) ? b : c0b);
