@@ -291,9 +291,9 @@ template <int N, int D> struct Exact {
         if constexpr (N > 1) {
 #pragma unroll
             for (int i = N - 2; i >= 1; --i)
-                if (e == u.ty[i])
+                if (__builtin_expect(e == u.ty[i], 0))
                     if (on && hit(i - 1, t)) push(i, t, c.lo[i], c.hi[i], status);
-            if (e == u.ty[0])
+            if (__builtin_expect(e == u.ty[0], 0))
                 if (on) push(0, t, c.lo[0], c.hi[0], status);
         }
     }
