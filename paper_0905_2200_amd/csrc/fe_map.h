@@ -469,23 +469,32 @@ template <int N, bool EXACT, int D> struct MainRun {
                 unsigned long long gp = ml & upto;
                 ml &= ~upto;
                 int cpos = -1, ct = 0;
-                if (gp) {
-                    int pos = (int)__builtin_ctzll(gp);
-                    int2 et = evs[pos];
-                    for (;;) {
-                        if (et.x == dty) {
-                            if (m.step_last(et.x, et.y, c)) {
-                                cpos = pos;
-                                ct = et.y;
-                                break;
-                            }
-                            // relaxed: a later tick cannot pass a test this one failed
-                            if (!EXACT) break;
+                if constexpr (EXACT) {
+                    // a later last-type event may enter a window an earlier one missed
+                    while (gp) {
+                        const int pos = (int)__builtin_ctzll(gp);
+                        const int2 et = evs[pos];
+                        // (et.x differs from dty only on a type-hash collision)
+                        if ((et.x == dty) & m.step_last(et.x, et.y, c)) {
+                            cpos = pos;
+                            ct = et.y;
+                            break;
                         }
                         gp &= gp - 1ull;
-                        if (!gp) break;
+                    }
+                } else if (gp) {
+                    // relaxed: only the first last-type event can pass (a later
+                    // tick cannot pass a test this one failed); the loop skips
+                    // type-hash collisions only
+                    int pos = (int)__builtin_ctzll(gp);
+                    int2 et = evs[pos];
+                    while (et.x != dty && (gp &= gp - 1ull)) {
                         pos = (int)__builtin_ctzll(gp);
                         et = evs[pos];
+                    }
+                    if ((et.x == dty) & m.step_last(et.x, et.y, c)) {
+                        cpos = pos;
+                        ct = et.y;
                     }
                 }
                 if (cpos >= 0) {
