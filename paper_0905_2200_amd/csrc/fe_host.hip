@@ -48,7 +48,7 @@ struct fe_ctx {
     fe_stats stats{};
     // workspace
     Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
-    Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn;
+    Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn, mkey;
     int *host = nullptr;  // pinned host staging for small readbacks
     size_t host_cap = 0;
     // kernel timing
@@ -569,7 +569,8 @@ extern "C" int fe_destroy(fe_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     Buf *bufs[] = {&c->keys, &c->hist, &c->wmax, &c->fill, &c->pk,    &c->orig,  &c->tileW,
                    &c->lam,  &c->tbl,  &c->flags, &c->sel, &c->nsel,  &c->status, &c->small, &c->cmask,
-                   &c->mtypes, &c->mlen, &c->mlo, &c->mhi, &c->mup, &c->mex, &c->msel, &c->mn};
+                   &c->mtypes, &c->mlen, &c->mlo, &c->mhi, &c->mup, &c->mex, &c->msel, &c->mn,
+                   &c->mkey};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &p : c->pending) {
@@ -955,8 +956,11 @@ int host_dcls(const int *k, int m, bool exact)
 }
 
 // order: the candidates to pack (indices into C), or null for all of C in
-// order; n: their number.
-void host_pack(const Episodes &C, const int *order, int64_t n, bool exact, HostPack &hp)
+// order; n: their number.  With wmax_bound >= 0 only the lane assignment
+// (hp.orig) and the groups are produced, each group's wmax set to that bound;
+// the records are then built on the device (k_build_rec) from C's keys.
+void host_pack(const Episodes &C, const int *order, int64_t n, bool exact, HostPack &hp,
+               int wmax_bound = -1)
 {
     const int m = C.m;
     const int ri = rec_ints(m);
@@ -1027,6 +1031,15 @@ void host_pack(const Episodes &C, const int *order, int64_t n, bool exact, HostP
             }
         });
         std::fill(lanes.begin() + run_tiles * WAVE + nmixed, lanes.end(), -1);
+        if (wmax_bound >= 0) {
+            GroupDesc gd{(m - 1) * NDCLS + cls, tiles, hp.tiles, (int64_t)hp.tiles * ri,
+                         wmax_bound, V};
+            if (hp.orig.empty()) hp.orig.swap(lanes);
+            else hp.orig.insert(hp.orig.end(), lanes.begin(), lanes.end());
+            hp.tiles += tiles;
+            hp.groups.push_back(gd);
+            continue;
+        }
         GroupDesc gd{(m - 1) * NDCLS + cls, tiles, hp.tiles, (int64_t)hp.rec.size(), 0, V};
         const size_t rec0 = hp.rec.size(), orig0 = hp.orig.size(), tw0 = hp.tileW.size();
         hp.rec.resize(rec0 + (size_t)tiles * ri);
@@ -1064,6 +1077,25 @@ void host_pack(const Episodes &C, const int *order, int64_t n, bool exact, HostP
         hp.tiles += tiles;
         hp.groups.push_back(gd);
     }
+}
+
+// Lanes-only pack: upload the lane assignment and build the tile records
+// and look-back widths on the device from the level's keys (key_d).
+int upload_lanes(fe_ctx *c, const HostPack &hp, const int *key_d, int m)
+{
+    int rc;
+    hipStream_t s = c->stream;
+    const size_t tiles = (size_t)hp.tiles;
+    if ((rc = ensure(c, c->pk, std::max<size_t>(tiles * rec_ints(m), 1) * sizeof(int)))) return rc;
+    if ((rc = ensure(c, c->orig, std::max<size_t>(hp.orig.size(), 1) * sizeof(int)))) return rc;
+    if ((rc = ensure(c, c->tileW, std::max<size_t>(tiles, 1) * sizeof(int)))) return rc;
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (!hp.orig.empty())
+        HIPCHK(c, hipMemcpyAsync(P<int>(c->orig), hp.orig.data(), hp.orig.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, s));
+    launch_build_rec(key_d, m, P<int>(c->orig), (int)tiles, P<int>(c->pk), P<int>(c->tileW), s);
+    HIPCHK(c, hipGetLastError());
+    return FE_OK;
 }
 
 int upload_pack(fe_ctx *c, const HostPack &hp)
@@ -1163,15 +1195,24 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         if ((rc = ensure(c, c->msel, M * sizeof(int)))) return rc;
         if ((rc = ensure(c, c->mn, 4 * sizeof(int)))) return rc;
         int *up = P<int>(c->mup), *ex = P<int>(c->mex);
+        // the level's keys go to the device once; tile records are built there
+        const int wbound = (level - 1) * *std::max_element(ihi.begin(), ihi.end());
+        if ((rc = ensure(c, c->mkey, std::max<size_t>(C.key.size(), 1) * sizeof(int)))) return rc;
+        {
+            HTimer ht(c, "host_upload");
+            HIPCHK(c, hipStreamSynchronize(s));
+            HIPCHK(c, hipMemcpyAsync(P<int>(c->mkey), C.key.data(), C.key.size() * sizeof(int),
+                                     hipMemcpyHostToDevice, s));
+        }
         // pass 1 (Algorithm 3) over every candidate
         HostPack hp;
         {
             HTimer ht(c, "host_pack");
-            host_pack(C, nullptr, (int64_t)M, false, hp);
+            host_pack(C, nullptr, (int64_t)M, false, hp, wbound);
         }
         {
             HTimer ht(c, "host_upload");
-            if ((rc = upload_pack(c, hp))) return rc;
+            if ((rc = upload_lanes(c, hp, P<int>(c->mkey), level))) return rc;
         }
         if ((rc = launch_groups(c, ids, ticks, si, hp.groups, false, up))) return rc;
         // elimination (Algorithm 4): survivors have upper >= theta
@@ -1189,11 +1230,11 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         if (nsurv > 0) {
             {
                 HTimer ht(c, "host_pack");
-                host_pack(C, order.data(), nsurv, true, hp);
+                host_pack(C, order.data(), nsurv, true, hp, wbound);
             }
             {
                 HTimer ht(c, "host_upload");
-                if ((rc = upload_pack(c, hp))) return rc;
+                if ((rc = upload_lanes(c, hp, P<int>(c->mkey), level))) return rc;
             }
             if ((rc = launch_groups(c, ids, ticks, si, hp.groups, true, ex))) return rc;
         }

@@ -103,6 +103,8 @@ void launch_fixup(int N, bool exact, int dcls, const MapGroup &g, hipStream_t s)
 void launch_persist(int N, bool exact, int dcls, const BatchDev &b, int grid, hipStream_t s);
 void launch_resume(int N, bool exact, int dcls, const MapGroup &g, int from, int *count_io,
                    int *last_io, hipStream_t s);
+void launch_build_rec(const int *key, int m, const int *orig, int tiles, int *rec, int *tileW,
+                      hipStream_t s);
 void launch_persist_fixup(int N, bool exact, int dcls, const BatchDev &b, const int *ctiles,
                           int nct, hipStream_t s);
 void launch_plan_batch(const TileDesc *tiles, const BJob *jobs, const int *tileW,

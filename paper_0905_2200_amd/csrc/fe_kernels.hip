@@ -542,6 +542,52 @@ void launch_gather2(const int *a, const int *b, const int *sel, const int *nsel,
                        out_b);
 }
 
+// Tile records of the mining driver, built on the device from the level's
+// episode keys (3m-2 ints each, interleaved (E1, lo1, hi1, E2, ..., E_m))
+// and the host's lane assignment orig[tile*64+lane] (-1 = padding): the
+// same layout the device grouping writes.  tileW[tile] = largest sum(hi).
+__global__ __launch_bounds__(WAVE *WPB) void k_build_rec(const int *__restrict__ key, int m,
+                                                         const int *__restrict__ orig, int tiles,
+                                                         int *__restrict__ rec,
+                                                         int *__restrict__ tileW)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int t = blockIdx.x * WPB + (threadIdx.x >> 6);
+    if (t >= tiles) return;
+    const int idx = orig[(int64_t)t * WAVE + lane];
+    int *r = rec + (int64_t)t * rec_ints(m);
+    int W = 0;
+    if (idx < 0) {
+        for (int k = 0; k < m; ++k) r[k * WAVE + lane] = -1;
+        for (int k = 0; k < m - 1; ++k) {
+            r[(m + k) * WAVE + lane] = 0;
+            r[(2 * m - 1 + k) * WAVE + lane] = 0;
+        }
+    } else {
+        const int *kk = key + (int64_t)idx * (3 * m - 2);
+        for (int k = 0; k < m; ++k) r[k * WAVE + lane] = kk[3 * k];
+        for (int k = 0; k < m - 1; ++k) {
+            const int hi = kk[3 * k + 2];
+            r[(m + k) * WAVE + lane] = kk[3 * k + 1];
+            r[(2 * m - 1 + k) * WAVE + lane] = hi;
+            W += hi;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(W, off);
+        W = o > W ? o : W;
+    }
+    if (lane == 0) tileW[t] = W;
+}
+
+void launch_build_rec(const int *key, int m, const int *orig, int tiles, int *rec, int *tileW,
+                      hipStream_t s)
+{
+    if (tiles <= 0) return;
+    hipLaunchKernelGGL(k_build_rec, dim3((unsigned)((tiles + WPB - 1) / WPB)), dim3(WAVE * WPB),
+                       0, s, key, m, orig, tiles, rec, tileW);
+}
+
 // out[c] = OR over the events of chunk c (indices 8c..8c+7) of 1 << (id & 63)
 __global__ void k_chunkmask(const int *__restrict__ ids, int n, unsigned long long *out)
 {
