@@ -87,17 +87,42 @@ def cpu_baseline(stream, target_s, n_types, intervals, theta):
         M_done += chunk
         if dt < target_s / 8:
             chunk *= 2
+    # single thread, plain configuration (all 4096 pairs over about 2e4 events)
+    pl = synth.config_plain()
+    pc = pl["candidates"]
+    reps, t0 = 0, time.perf_counter()
+    while reps == 0 or time.perf_counter() - t0 < 1.0:
+        up1, _ = oracle.two_pass(pl["ids"], pl["ticks"], 64, pc["types"], pc["len"], pc["lo"],
+                                 pc["hi"], pl["theta"], projection=True, nthreads=1)
+        reps += 1
+    dt1 = time.perf_counter() - t0
+    ee1 = reps * float(pc["M"] + int((up1 >= pl["theta"]).sum())) * pl["ids"].size
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": total_ee / total_s, "unit": "ee/s", "cores": threads, "kind": "oracle",
             "sample": ("two-pass (relaxed pass, elimination, exact pass) in projection mode on "
                        "%d random level-3 episodes of the mining workload over its %d events, "
-                       "%.1f s" % (M_done, ids.size, total_s))}
+                       "%.1f s" % (M_done, ids.size, total_s)),
+            "cpu_model": model,
+            "single_thread_plain": {"value": float("%.4g" % (ee1 / dt1)),
+                                    "unit": "ee/s",
+                                    "sample": "two-pass over the 4096 pairs of the plain "
+                                              "configuration (%d events), 1 thread, %d runs "
+                                              "in %.2f s" % (pl["ids"].size, reps, dt1)}}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--duration-s", type=float, default=780.0,
                     help="stream duration of the mining workload (default 780 s)")
     ap.add_argument("--max-level", type=int, default=6)
@@ -112,6 +137,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="served: requests per second")
     ap.add_argument("--partition-s", type=float, default=10.0,
                     help="streaming: seconds of recording per partition")
+    ap.add_argument("--one-pass", action="store_true",
+                    help="mining: Algorithm 1 over every candidate, no elimination pass")
     ap.add_argument("--type-dispatch", type=int, default=1, choices=[0, 1],
                     help="per-type dispatch for shared-prefix waves (0 = every event)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -147,6 +174,7 @@ def main():
 
     ctx = fe.Context(0)
     ctx.set_param(fe.PARAM_TYPE_DISPATCH, args.type_dispatch)
+    ctx.set_param(fe.PARAM_ELIMINATION, 0 if args.one_pass else 1)
     ids, ticks = ctx.stream_tensors(s["ids"], s["ticks"])
     torch.cuda.synchronize()
 
@@ -183,7 +211,8 @@ def main():
     kst = ctx.kernel_stats()
     ctx.set_param(fe.PARAM_TIMING, 0)
 
-    ee_step = sum((lv["n_candidates"] + lv["n_survivors"]) * n for lv in res if lv["level"] >= 2)
+    ee_step = sum((lv["n_candidates"] + (0 if args.one_pass else lv["n_survivors"])) * n
+                  for lv in res if lv["level"] >= 2)
     value = ee_step * args.steps / t_total
     for lv in res:
         log("level %d: candidates %d survivors %d frequent %d gen %.1f ms count %.1f ms" % (
@@ -233,7 +262,9 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "level-wise mining, two-pass, levels 2-%d" % args.max_level,
+        "config": {"workload": "level-wise mining, %s, levels 2-%d" % (
+                       "one pass (no elimination)" if args.one_pass else "two-pass",
+                       args.max_level),
                    "neurons": s["num_types"], "rate_hz": 20, "duration_s": args.duration_s,
                    "n_events": n, "theta": theta, "intervals_ticks": intervals,
                    "ee_per_step": ee_step,

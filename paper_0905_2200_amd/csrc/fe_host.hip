@@ -44,7 +44,7 @@ struct fe_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
-    int64_t param[8] = {0, 4096, 1024, 1, 0, 1, 24200, 6926};
+    int64_t param[9] = {0, 4096, 1024, 1, 0, 1, 24200, 6926, 1};
     fe_stats stats{};
     // workspace
     Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
@@ -609,7 +609,7 @@ extern "C" int fe_sync(fe_ctx *c)
 extern "C" int fe_set_param(fe_ctx *c, int param, int64_t value)
 {
     if (!c) return FE_EINVAL;
-    if (param < 0 || param > 7 || value < 0) return fail(c, FE_EINVAL, "bad parameter");
+    if (param < 0 || param > 8 || value < 0) return fail(c, FE_EINVAL, "bad parameter");
     if (param == FE_PARAM_TARGET_WAVES && value == 0) return fail(c, FE_EINVAL, "bad parameter");
     c->param[param] = value;
     return FE_OK;
@@ -617,7 +617,7 @@ extern "C" int fe_set_param(fe_ctx *c, int param, int64_t value)
 
 extern "C" int fe_get_param(const fe_ctx *c, int param, int64_t *value)
 {
-    if (!c || !value || param < 0 || param > 7) return FE_EINVAL;
+    if (!c || !value || param < 0 || param > 8) return FE_EINVAL;
     *value = c->param[param];
     return FE_OK;
 }
@@ -1204,33 +1204,41 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
             HIPCHK(c, hipMemcpyAsync(P<int>(c->mkey), C.key.data(), C.key.size() * sizeof(int),
                                      hipMemcpyHostToDevice, s));
         }
-        // pass 1 (Algorithm 3) over every candidate
         HostPack hp;
-        {
-            HTimer ht(c, "host_pack");
-            host_pack(C, nullptr, (int64_t)M, false, hp, wbound);
-        }
-        {
-            HTimer ht(c, "host_upload");
-            if ((rc = upload_lanes(c, hp, P<int>(c->mkey), level))) return rc;
-        }
-        if ((rc = launch_groups(c, ids, ticks, si, hp.groups, false, up))) return rc;
-        // elimination (Algorithm 4): survivors have upper >= theta
-        ivec uph(M), order;
-        HIPCHK(c, hipStreamSynchronize(s));
-        {
-            HTimer ht(c, "host_select");
-            HIPCHK(c, hipMemcpyAsync(uph.data(), up, M * sizeof(int), hipMemcpyDeviceToHost, s));
+        ivec order;
+        const bool elim = c->param[FE_PARAM_ELIMINATION] != 0;
+        if (elim) {
+            // pass 1 (Algorithm 3) over every candidate
+            {
+                HTimer ht(c, "host_pack");
+                host_pack(C, nullptr, (int64_t)M, false, hp, wbound);
+            }
+            {
+                HTimer ht(c, "host_upload");
+                if ((rc = upload_lanes(c, hp, P<int>(c->mkey), level))) return rc;
+            }
+            if ((rc = launch_groups(c, ids, ticks, si, hp.groups, false, up))) return rc;
+            // elimination (Algorithm 4): survivors have upper >= theta
+            ivec uph(M);
             HIPCHK(c, hipStreamSynchronize(s));
-            par_select((int64_t)M, [&](int64_t i) { return uph[i] >= theta; }, order);
+            {
+                HTimer ht(c, "host_select");
+                HIPCHK(c, hipMemcpyAsync(uph.data(), up, M * sizeof(int), hipMemcpyDeviceToHost,
+                                         s));
+                HIPCHK(c, hipStreamSynchronize(s));
+                par_select((int64_t)M, [&](int64_t i) { return uph[i] >= theta; }, order);
+            }
+        } else {
+            // one pass: Algorithm 1 over every candidate, no relaxed count
+            launch_fill(up, -1, (int64_t)M, s);
         }
-        const int64_t nsurv = (int64_t)order.size();
+        const int64_t nsurv = elim ? (int64_t)order.size() : (int64_t)M;
         // pass 2 (Algorithm 1) over the survivors; the others keep -1
         launch_fill(ex, -1, (int64_t)M, s);
         if (nsurv > 0) {
             {
                 HTimer ht(c, "host_pack");
-                host_pack(C, order.data(), nsurv, true, hp, wbound);
+                host_pack(C, elim ? order.data() : nullptr, nsurv, true, hp, wbound);
             }
             {
                 HTimer ht(c, "host_upload");

@@ -173,3 +173,24 @@ def test_hybrid_crossover_rule(ctx, fe):
     finally:
         ctx.set_param(fe.PARAM_CROSSOVER_A, A0)
         ctx.set_param(fe.PARAM_CROSSOVER_B, B0)
+
+
+def test_one_pass_mining_same_result(ctx, fe):
+    # Algorithm 1 over every candidate (no elimination) finds the same frequent
+    # episodes with the same exact counts as the two-pass form
+    s = synth.config_mining(duration_s=60.0)
+    ids, ticks = ctx.stream_tensors(s["ids"], s["ticks"])
+    res = {}
+    for elim in (1, 0):
+        ctx.set_param(fe.PARAM_ELIMINATION, elim)
+        try:
+            res[elim] = ctx.mine(ids, ticks, s["num_types"], s["intervals"], s["theta"], 5)
+        finally:
+            ctx.set_param(fe.PARAM_ELIMINATION, 1)
+    assert len(res[0]) == len(res[1])
+    for a, b in zip(res[1], res[0]):
+        for k in ("types", "lo", "hi", "exact"):
+            assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (a["level"], k)
+        if a["level"] >= 2:
+            assert (np.asarray(b["upper"]) == -1).all()
+            assert b["n_survivors"] == b["n_candidates"]
