@@ -191,9 +191,12 @@ template <int N, int D> struct Exact {
     __device__ __forceinline__ void push(int k, int t, int lo, int hi, int *status)
     {
         const int a = t + lo + 1, b = t + hi;
+        // (D = 1 and 2: an unused slot has end GONE, so "ended before t" and
+        // "unused" are one test; lane masks are combined bitwise, without
+        // divergent control flow)
         if constexpr (D == 1) {
             // one live window at most: start anew, extend, or (invariant) fail
-            const bool gone = (wb[k][0] < t) | (wb[k][0] == EMPTY);
+            const bool gone = wb[k][0] < t;
             const bool mrg = !gone & (wb[k][0] >= a - 1);
             if (!gone & !mrg) atomicOr(status, ST_INTERNAL);
             wa[k][0] = mrg ? wa[k][0] : a;
@@ -205,16 +208,15 @@ template <int N, int D> struct Exact {
             // extend the last live window or append after it
             const bool x0 = wb[k][0] < t;
             const int c0a = x0 ? wa[k][1] : wa[k][0], c0b = x0 ? wb[k][1] : wb[k][0];
-            const int c1a = x0 ? EMPTY : wa[k][1], c1b = x0 ? EMPTY : wb[k][1];
-            const bool gone = (c0b < t) | (c0b == EMPTY);  // no live window left
-            const bool two = !gone & (c1b != EMPTY);
-            // (lane masks combined bitwise: no divergent control flow)
+            const int c1a = wa[k][1], c1b = x0 ? GONE : wb[k][1];
+            const bool gone = c0b < t;  // no live window left
+            const bool two = c1b >= t;  // two live windows
             const bool mrg = (two & (c1b >= a - 1)) | (!two & !gone & (c0b >= a - 1));
             if (two & !mrg) atomicOr(status, ST_INTERNAL);
             wa[k][0] = gone ? a : c0a;
             wb[k][0] = gone ? b : ((!two & mrg) ? b : c0b);
-            wa[k][1] = gone ? EMPTY : (two ? c1a : (mrg ? EMPTY : a));
-            wb[k][1] = gone ? EMPTY : (two ? (mrg ? b : c1b) : (mrg ? EMPTY : b));
+            wa[k][1] = two ? c1a : a;
+            wb[k][1] = gone ? GONE : (two ? (mrg ? b : c1b) : (mrg ? GONE : b));
             return;
         }
         int nd = 0;
@@ -292,7 +294,7 @@ template <int N, int D> struct Exact {
 #pragma unroll
             for (int i = N - 2; i >= 1; --i)
                 if (__builtin_expect(e == u.ty[i], 0))
-                    if (on && hit(i - 1, t)) push(i, t, c.lo[i], c.hi[i], status);
+                    if (on & hit(i - 1, t)) push(i, t, c.lo[i], c.hi[i], status);
             if (__builtin_expect(e == u.ty[0], 0))
                 if (on) push(0, t, c.lo[0], c.hi[0], status);
         }
