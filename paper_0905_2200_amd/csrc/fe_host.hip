@@ -30,6 +30,57 @@ struct Buf {
     size_t cap = 0;
 };
 
+// Large host arrays are written in full by the loops that fill them, so they
+// are allocated without value-initialisation.  Arrays of 64 MB and more
+// (the candidate keys of a big level) go to pinned host memory, so their
+// upload is an asynchronous DMA; the mining driver keeps such a buffer for
+// reuse, so it is pinned once.
+std::mutex g_pin_mu;
+std::unordered_map<void *, size_t> g_pinned;  // pinned blocks from NoInit::allocate
+
+template <class T> struct NoInit : std::allocator<T> {
+    static constexpr size_t PIN_BYTES = (size_t)64 << 20;
+    template <class U> struct rebind {
+        typedef NoInit<U> other;
+    };
+    NoInit() = default;
+    template <class U> NoInit(const NoInit<U> &) {}
+    T *allocate(size_t n)
+    {
+        if (n * sizeof(T) >= PIN_BYTES) {
+            void *p = nullptr;
+            if (hipHostMalloc(&p, n * sizeof(T), hipHostMallocDefault) == hipSuccess && p) {
+                std::lock_guard<std::mutex> lk(g_pin_mu);
+                g_pinned[p] = n;
+                return (T *)p;
+            }
+            (void)hipGetLastError();
+        }
+        return std::allocator<T>::allocate(n);
+    }
+    void deallocate(T *p, size_t n)
+    {
+        if (n * sizeof(T) >= PIN_BYTES) {
+            std::lock_guard<std::mutex> lk(g_pin_mu);
+            auto it = g_pinned.find((void *)p);
+            if (it != g_pinned.end()) {
+                g_pinned.erase(it);
+                (void)hipHostFree(p);
+                return;
+            }
+        }
+        std::allocator<T>::deallocate(p, n);
+    }
+    template <class U> void construct(U *p) noexcept { ::new ((void *)p) U; }
+    template <class U, class... A> void construct(U *p, A &&...a)
+    {
+        ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+template <class T, class U> bool operator==(const NoInit<T> &, const NoInit<U> &) { return true; }
+template <class T, class U> bool operator!=(const NoInit<T> &, const NoInit<U> &) { return false; }
+typedef std::vector<int, NoInit<int>> ivec;
+
 double now_ms()
 {
     return std::chrono::duration<double, std::milli>(
@@ -49,6 +100,8 @@ struct fe_ctx {
     // workspace
     Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
     Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn, mkey;
+    // host arrays of the mining driver, kept for reuse (large ones are pinned)
+    ivec keypool, lanepool, uphpool, orderpool;
     int *host = nullptr;  // pinned host staging for small readbacks
     size_t host_cap = 0;
     // kernel timing
@@ -745,21 +798,6 @@ extern "C" int fe_count_resume(fe_ctx *c, const int32_t *ids, const int32_t *tic
 
 namespace {
 
-// Large host arrays are written in full by the loops that fill them, so they
-// are allocated without value-initialisation.
-template <class T> struct NoInit : std::allocator<T> {
-    template <class U> struct rebind {
-        typedef NoInit<U> other;
-    };
-    NoInit() = default;
-    template <class U> NoInit(const NoInit<U> &) {}
-    template <class U> void construct(U *p) noexcept { ::new ((void *)p) U; }
-    template <class U, class... A> void construct(U *p, A &&...a)
-    {
-        ::new ((void *)p) U(std::forward<A>(a)...);
-    }
-};
-typedef std::vector<int, NoInit<int>> ivec;
 
 // Host worker threads for candidate generation and packing.
 int host_threads()
@@ -960,7 +998,7 @@ int host_dcls(const int *k, int m, bool exact)
 // (hp.orig) and the groups are produced, each group's wmax set to that bound;
 // the records are then built on the device (k_build_rec) from C's keys.
 void host_pack(const Episodes &C, const int *order, int64_t n, bool exact, HostPack &hp,
-               int wmax_bound = -1)
+               int wmax_bound = -1, ivec *lane_pool = nullptr)
 {
     const int m = C.m;
     const int ri = rec_ints(m);
@@ -970,14 +1008,15 @@ void host_pack(const Episodes &C, const int *order, int64_t n, bool exact, HostP
     hp.groups.clear();
     hp.tiles = 0;
     auto cand = [&](int64_t i) { return order ? order[i] : (int)i; };
-    // depth classes, stable
+    // depth classes, stable (all of C in order: one class, the identity)
+    const bool ident = !exact && !order;
     ivec byc[NDCLS];
-    if (!exact) {
+    if (!exact && !ident) {
         byc[0].resize(n);
         par_for(n, 65536, [&](int64_t b, int64_t e, int) {
             for (int64_t i = b; i < e; ++i) byc[0][i] = cand(i);
         });
-    } else {
+    } else if (exact) {
         ivec cls(n);
         par_for(n, 65536, [&](int64_t b, int64_t e, int) {
             for (int64_t i = b; i < e; ++i) cls[i] = host_dcls(C.at(cand(i)), m, true);
@@ -999,11 +1038,20 @@ void host_pack(const Episodes &C, const int *order, int64_t n, bool exact, HostP
     };
     for (int cls = 0; cls < NDCLS; ++cls) {
         const ivec &v = byc[cls];
-        const int64_t V = (int64_t)v.size();
+        const int64_t V = ident ? (cls == 0 ? n : 0) : (int64_t)v.size();
         if (V == 0) continue;
+        auto vat = [&](int64_t i) { return ident ? (int)i : v[i]; };
+        // copy v[s0, s0+len) to dst
+        auto vcopy = [&](int *dst, int64_t s0, int64_t len) {
+            if (ident)
+                for (int64_t j = 0; j < len; ++j) dst[j] = (int)(s0 + j);
+            else
+                std::memcpy(dst, v.data() + s0, len * sizeof(int));
+        };
         // runs of equal first m-1 types
         ivec starts;
-        par_select(V, [&](int64_t i) { return i == 0 || !same_prefix(v[i - 1], v[i]); }, starts);
+        par_select(V, [&](int64_t i) { return i == 0 || !same_prefix(vat(i - 1), vat(i)); },
+                   starts);
         const int64_t R = (int64_t)starts.size();
         std::vector<int64_t> toff(R + 1, 0), moff(R + 1, 0);
         for (int64_t r = 0; r < R; ++r) {
@@ -1014,19 +1062,20 @@ void host_pack(const Episodes &C, const int *order, int64_t n, bool exact, HostP
         }
         const int64_t run_tiles = toff[R], nmixed = moff[R];
         const int tiles = (int)(run_tiles + (nmixed + WAVE - 1) / WAVE);
-        ivec lanes((size_t)tiles * WAVE);
+        ivec lanes;
+        if (lane_pool && hp.orig.empty()) lanes.swap(*lane_pool);
+        lanes.resize((size_t)tiles * WAVE);
         par_for(R, 1024, [&](int64_t b, int64_t e, int) {
             for (int64_t r = b; r < e; ++r) {
                 const int64_t s0 = starts[r], len = (r + 1 < R ? starts[r + 1] : V) - s0;
                 const int64_t full = len / WAVE * WAVE, rem = len - full;
                 int *dst = lanes.data() + toff[r] * WAVE;
-                std::memcpy(dst, v.data() + s0, full * sizeof(int));
+                vcopy(dst, s0, full);
                 if (rem >= WAVE / 2) {
-                    std::memcpy(dst + full, v.data() + s0 + full, rem * sizeof(int));
+                    vcopy(dst + full, s0 + full, rem);
                     std::fill(dst + full + rem, dst + full + WAVE, -1);
                 } else {
-                    std::memcpy(lanes.data() + run_tiles * WAVE + moff[r], v.data() + s0 + full,
-                                rem * sizeof(int));
+                    vcopy(lanes.data() + run_tiles * WAVE + moff[r], s0 + full, rem);
                 }
             }
         });
@@ -1179,6 +1228,7 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
     for (int level = 2; level <= max_level && F.count() > 0 && n_iv > 0; ++level) {
         t0 = now_ms();
         Episodes C;
+        C.key.swap(c->keypool);
         {
             HTimer ht(c, "host_gen");
             if (level == 2) gen_level2(levels[0].types, ilo, ihi, C);
@@ -1199,8 +1249,8 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         const int wbound = (level - 1) * *std::max_element(ihi.begin(), ihi.end());
         if ((rc = ensure(c, c->mkey, std::max<size_t>(C.key.size(), 1) * sizeof(int)))) return rc;
         {
+            // (pinned when large: the copy overlaps the host tiling below)
             HTimer ht(c, "host_upload");
-            HIPCHK(c, hipStreamSynchronize(s));
             HIPCHK(c, hipMemcpyAsync(P<int>(c->mkey), C.key.data(), C.key.size() * sizeof(int),
                                      hipMemcpyHostToDevice, s));
         }
@@ -1211,7 +1261,7 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
             // pass 1 (Algorithm 3) over every candidate
             {
                 HTimer ht(c, "host_pack");
-                host_pack(C, nullptr, (int64_t)M, false, hp, wbound);
+                host_pack(C, nullptr, (int64_t)M, false, hp, wbound, &c->lanepool);
             }
             {
                 HTimer ht(c, "host_upload");
@@ -1219,8 +1269,12 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
             }
             if ((rc = launch_groups(c, ids, ticks, si, hp.groups, false, up))) return rc;
             // elimination (Algorithm 4): survivors have upper >= theta
-            ivec uph(M);
+            ivec uph;
+            uph.swap(c->uphpool);
+            uph.resize(M);
+            order.swap(c->orderpool);
             HIPCHK(c, hipStreamSynchronize(s));
+            c->lanepool.swap(hp.orig);  // its upload has completed
             {
                 HTimer ht(c, "host_select");
                 HIPCHK(c, hipMemcpyAsync(uph.data(), up, M * sizeof(int), hipMemcpyDeviceToHost,
@@ -1228,6 +1282,7 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
                 HIPCHK(c, hipStreamSynchronize(s));
                 par_select((int64_t)M, [&](int64_t i) { return uph[i] >= theta; }, order);
             }
+            c->uphpool.swap(uph);
         } else {
             // one pass: Algorithm 1 over every candidate, no relaxed count
             launch_fill(up, -1, (int64_t)M, s);
@@ -1238,7 +1293,8 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         if (nsurv > 0) {
             {
                 HTimer ht(c, "host_pack");
-                host_pack(C, elim ? order.data() : nullptr, nsurv, true, hp, wbound);
+                host_pack(C, elim ? order.data() : nullptr, nsurv, true, hp, wbound,
+                          &c->lanepool);
             }
             {
                 HTimer ht(c, "host_upload");
@@ -1295,6 +1351,10 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         levels.push_back(std::move(Lv));
         F.m = level;
         F.key.swap(NF.key);
+        // (their copies to the device have completed: synchronised above)
+        c->keypool.swap(C.key);
+        if (hp.orig.capacity() > c->lanepool.capacity()) c->lanepool.swap(hp.orig);
+        c->orderpool.swap(order);
     }
 
     fe_result *r = (fe_result *)std::calloc(1, sizeof(fe_result));
