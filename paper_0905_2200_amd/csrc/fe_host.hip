@@ -1017,18 +1017,43 @@ void host_pack(const Episodes &C, const int *order, int64_t n, bool exact, HostP
             for (int64_t i = b; i < e; ++i) byc[0][i] = cand(i);
         });
     } else if (exact) {
+        // one pass counting per part and class, then a stable scatter
         ivec cls(n);
-        par_for(n, 65536, [&](int64_t b, int64_t e, int) {
-            for (int64_t i = b; i < e; ++i) cls[i] = host_dcls(C.at(cand(i)), m, true);
+        const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(),
+                                                                        n / 65536));
+        std::vector<int64_t> cnt((size_t)parts * NDCLS, 0);
+        auto range = [&](int q, int64_t &b, int64_t &e) {
+            b = n * q / parts;
+            e = n * (q + 1) / parts;
+        };
+        par_for(parts, 1, [&](int64_t q0, int64_t q1, int) {
+            for (int64_t q = q0; q < q1; ++q) {
+                int64_t b, e;
+                range((int)q, b, e);
+                for (int64_t i = b; i < e; ++i) {
+                    cls[i] = host_dcls(C.at(cand(i)), m, true);
+                    ++cnt[q * NDCLS + cls[i]];
+                }
+            }
         });
+        std::vector<int64_t> off((size_t)parts * NDCLS);
         for (int k = 0; k < NDCLS; ++k) {
-            ivec sel;
-            par_select(n, [&](int64_t i) { return cls[i] == k; }, sel);
-            byc[k].resize(sel.size());
-            par_for((int64_t)sel.size(), 65536, [&](int64_t b, int64_t e, int) {
-                for (int64_t i = b; i < e; ++i) byc[k][i] = cand(sel[i]);
-            });
+            int64_t acc = 0;
+            for (int q = 0; q < parts; ++q) {
+                off[q * NDCLS + k] = acc;
+                acc += cnt[q * NDCLS + k];
+            }
+            byc[k].resize(acc);
         }
+        par_for(parts, 1, [&](int64_t q0, int64_t q1, int) {
+            for (int64_t q = q0; q < q1; ++q) {
+                int64_t b, e;
+                range((int)q, b, e);
+                int64_t o[NDCLS];
+                for (int k = 0; k < NDCLS; ++k) o[k] = off[q * NDCLS + k];
+                for (int64_t i = b; i < e; ++i) byc[cls[i]][o[cls[i]]++] = cand(i);
+            }
+        });
     }
     auto same_prefix = [&](int a, int b) {
         const int *x = C.at(a), *y = C.at(b);
