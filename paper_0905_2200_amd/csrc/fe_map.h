@@ -4,13 +4,16 @@
 // Instantiated per episode size N in fe_map_n<N>.hip.
 //
 // Mapping (CDNA4, wave64): one lane = one candidate's machine; one wave = a
-// tile of 64 candidates over one segment.  Every lane reads the same event,
-// so events come through scalar loads in the constant address space (one
-// SMEM fetch serves 64 machines) and machine state stays in VGPRs.
+// tile of 64 candidates over one segment; machine state stays in VGPRs.
 // Candidates produced by the level-wise join arrive in tiles whose first
-// N-1 node types are the same in every lane; such waves take a path where
-// those nodes are tested with scalar compares and only the last node is
-// per lane.
+// N-1 node types are the same in every lane; such waves test those nodes
+// with scalar compares and only the last node per lane.  Two ways of
+// feeding events (chosen per launch):
+//  * per-type dispatch (sparse, sparse_lane): 64 events per vector load,
+//    one per lane, with a per-block LDS table from type hash to event
+//    positions, so that a lane steps only the events of its own types;
+//  * every event through every lane (body): events through scalar loads in
+//    the constant address space, one SMEM fetch serving 64 machines.
 //
 // Counting semantics: for each event, nodes are visited from N down to 1
 // against the state before the event; a node-i match whose hop test passes
