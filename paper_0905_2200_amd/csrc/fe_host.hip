@@ -275,7 +275,8 @@ struct CandIn {
 
 struct StreamInfo {
     int n;
-    int span;  // ticks[n-1] - ticks[0] + 1
+    int span;       // ticks[n-1] - ticks[0] + 1
+    int num_types;  // ids lie in [0, num_types) (validated)
 };
 
 // Segment count P for a group of `tiles` tiles of N-node candidates: the
@@ -358,6 +359,7 @@ int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo 
         g.flags = nullptr;
         g.P = rs ? 1 : choose_P(c, tiles, si, gd.wmax, N);
         g.sparse = c->param[FE_PARAM_TYPE_DISPATCH] != 0;
+        g.hashx = si.num_types <= 64;
         c->stats.map_launches++;
         if (rs) {
             char rname[40];
@@ -509,6 +511,7 @@ int stream_info(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int n, int 
     int rc;
     si.n = n;
     si.span = 1;
+    si.num_types = num_types;
     if (n == 0) return FE_OK;
     launch_validate(ids, ticks, n, num_types, P<int>(c->status), c->stream);
     if ((rc = ensure_host(c, 4))) return rc;

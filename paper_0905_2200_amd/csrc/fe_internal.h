@@ -46,6 +46,7 @@ struct MapGroup {
     int tiles;
     int P;
     int sparse;  // shared-prefix waves use per-type dispatch
+    int hashx;   // every type id is below 64: the type hash (id & 63) is the id
 };
 
 // Batched counting (many recordings): one descriptor per recording and per

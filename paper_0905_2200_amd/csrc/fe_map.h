@@ -438,7 +438,8 @@ template <int N, bool EXACT, int D> struct MainRun {
     // 64-entry LDS scratch.
     template <bool NOTE>
     __device__ void sparse(const int *ids, const int *ticks, int b, int e, const Cand<N> &c,
-                           const Prefix<N> &u, unsigned long long *tm, int2 *evs, int *status)
+                           const Prefix<N> &u, unsigned long long *tm, int2 *evs, int *status,
+                           bool hx)
     {
         static_assert(N >= 2, "per-type dispatch needs a shared prefix");
         b = uniform(b);
@@ -474,7 +475,28 @@ template <int N, bool EXACT, int D> struct MainRun {
                 unsigned long long gp = ml & upto;
                 ml &= ~upto;
                 int cpos = -1, ct = 0;
-                if constexpr (EXACT) {
+                if (hx) {
+                    // type ids below 64: every position in gp holds the last type
+                    if constexpr (EXACT) {
+                        while (gp) {
+                            const int pos = (int)__builtin_ctzll(gp);
+                            const int t = evs[pos].y;
+                            if (m.step_last(dty, t, c)) {
+                                cpos = pos;
+                                ct = t;
+                                break;
+                            }
+                            gp &= gp - 1ull;
+                        }
+                    } else if (gp) {
+                        const int pos = (int)__builtin_ctzll(gp);
+                        const int t = evs[pos].y;
+                        if (m.step_last(dty, t, c)) {
+                            cpos = pos;
+                            ct = t;
+                        }
+                    }
+                } else if constexpr (EXACT) {
                     // a later last-type event may enter a window an earlier one missed
                     while (gp) {
                         const int pos = (int)__builtin_ctzll(gp);
@@ -727,6 +749,7 @@ struct ItemArgs {
     int *status;
     const unsigned long long *cmask;  // per aligned 8-event chunk type masks, or null
     const int *gids, *gticks;         // the same stream for vector loads
+    bool hashx;                       // every type id is below 64
     unsigned long long *tm;           // this wave's LDS scratch (per-type dispatch)
     int2 *evs;
 };
@@ -750,7 +773,8 @@ __device__ __forceinline__ void map_item(const ItemArgs &a, int o, bool valid)
             bool done = false;
             if constexpr (N >= 2) {
                 if (uni) {
-                    r.template sparse<NOTE>(a.gids, a.gticks, b, e, cd, u, a.tm, a.evs, a.status);
+                    r.template sparse<NOTE>(a.gids, a.gticks, b, e, cd, u, a.tm, a.evs, a.status,
+                                            a.hashx);
                     done = true;
                 }
             }
@@ -832,6 +856,7 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map(const int *__restrict__ ids_,
     a.gticks = ticks_;
     a.tm = s_tm[threadIdx.x >> 6];
     a.evs = s_ev[threadIdx.x >> 6];
+    a.hashx = g.hashx != 0;
     map_item<N, EXACT, D, SPARSE>(a, o, o >= 0);
 }
 
@@ -862,7 +887,7 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map1(const int *__restrict__ ids_
         if constexpr (N >= 2) {
             if (uni) {
                 r.template sparse<false>(ids_, ticks_, 0, g.n, cd, u, s_tm[wv], s_ev[wv],
-                                         g.status);
+                                         g.status, g.hashx != 0);
                 done = true;
             }
         }
@@ -948,7 +973,7 @@ __global__ __launch_bounds__(WAVE *WPB) void k_resume(const int *__restrict__ id
         if constexpr (N >= 2) {
             if (uni) {
                 r.template sparse<false>(ids_, ticks_, smax, n, cd, u, s_tm[wv], s_ev[wv],
-                                         g.status);
+                                         g.status, g.hashx != 0);
                 done = true;
             }
         }
@@ -1013,6 +1038,7 @@ __global__ __launch_bounds__(WAVE *WPB) void k_persist(BatchDev b)
         a.gticks = jb.ticks;
         a.tm = s_tm[threadIdx.x >> 6];
         a.evs = s_ev[threadIdx.x >> 6];
+        a.hashx = false;
         map_item<N, EXACT, D, SPARSE>(a, o, valid);
     }
 }
