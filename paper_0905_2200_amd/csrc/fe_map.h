@@ -191,6 +191,18 @@ template <int N, int D> struct Exact {
         for (int d = 0; d < D; ++d) h |= (wa[k][d] <= t) & (t <= wb[k][d]);
         return h;
     }
+    // Latest tick a window of list k covers (GONE when the list is empty):
+    // no later tick can pass that list's test.
+    __device__ __forceinline__ int end_of(int k) const
+    {
+        int r = GONE;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int w = (D > 2 && wb[k][d] == EMPTY) ? GONE : wb[k][d];
+            r = w > r ? w : r;
+        }
+        return r;
+    }
     __device__ __forceinline__ void push(int k, int t, int lo, int hi, int *status)
     {
         const int a = t + lo + 1, b = t + hi;
@@ -468,6 +480,7 @@ template <int N, bool EXACT, int D> struct MainRun {
             if (v) atomicOr(&tm[h], 1ull << lane);
             unsigned long long ml = tm[dh];
             unsigned long long remp = pm, remb = bm;
+            const int tk0 = __builtin_amdgcn_readfirstlane(tk);
             for (;;) {
                 // span: positions up to the lowest closing event (all if none)
                 const unsigned long long rb1 = remb - 1ull;
@@ -475,14 +488,24 @@ template <int N, bool EXACT, int D> struct MainRun {
                 unsigned long long gp = ml & upto;
                 ml &= ~upto;
                 int cpos = -1, ct = 0;
+                int lim = 0;
+                if constexpr (EXACT) {
+                    // list N-2 is fixed within the span; a lane whose windows
+                    // all end before the block's first tick cannot complete
+                    lim = m.end_of(N - 2);
+                    if (lim < tk0) gp = 0;
+                }
                 if (hx) {
                     // type ids below 64: every position in gp holds the last type
                     if constexpr (EXACT) {
                         while (gp) {
                             const int pos = (int)__builtin_ctzll(gp);
                             const int t = evs[pos].y;
-                            if (m.step_last(dty, t, c)) {
-                                cpos = pos;
+                            const bool pass = m.step_last(dty, t, c);
+                            if (pass | (t >= lim)) {
+                                // (ticks do not decrease: past the last window
+                                // no later event passes)
+                                cpos = pass ? pos : -1;
                                 ct = t;
                                 break;
                             }
@@ -507,6 +530,7 @@ template <int N, bool EXACT, int D> struct MainRun {
                             ct = et.y;
                             break;
                         }
+                        if (et.y > lim) break;
                         gp &= gp - 1ull;
                     }
                 } else if (gp) {
