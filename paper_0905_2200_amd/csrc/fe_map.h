@@ -133,6 +133,8 @@ template <int N> struct Relaxed {
         if constexpr (N == 1) return e == c.ty[0];
         else return (e == c.ty[N - 1]) & (t <= dl[N - 2]);
     }
+    // Latest tick list k's test passes at (-1 when empty).
+    __device__ __forceinline__ int end_of(int k) const { return dl[k]; }
     // Nodes 0..N-2 have wave-uniform types u.ty: scalar tests, rare updates.
     __device__ __forceinline__ bool step_u(int e, int t, const Cand<N> &c, const Prefix<N> &u,
                                            int *)
@@ -461,6 +463,7 @@ template <int N, bool EXACT, int D> struct MainRun {
         const int dty = c.ty[N - 1];
         const int dh = dty & 63;
         const int bh = u.ty[N - 2] & 63;
+        const int ah = u.ty[N >= 3 ? N - 3 : 0] & 63;
         const int lane4 = lane * 4;
         for (int cb = b; cb < e; cb += EV_CHUNK) {
         const int ce = e - cb > EV_CHUNK ? cb + EV_CHUNK : e;
@@ -481,6 +484,17 @@ template <int N, bool EXACT, int D> struct MainRun {
             unsigned long long ml = tm[dh];
             unsigned long long remp = pm, remb = bm;
             const int tk0 = __builtin_amdgcn_readfirstlane(tk);
+            if constexpr (N >= 3) {
+                // A node N-2 event changes list N-2 only in a lane whose list
+                // N-3 passes at its tick.  When no lane's list N-3 reaches the
+                // block's first tick, that needs a node N-3 push earlier in
+                // the block, so the events before the first node N-3 event
+                // close no span.
+                if (__builtin_amdgcn_ballot_w64(m.end_of(N - 3) >= tk0) == 0) {
+                    const unsigned long long am = __builtin_amdgcn_ballot_w64(v & (h == ah));
+                    remb = am ? (bm & ~(((am & (0ull - am)) << 1) - 1ull)) : 0ull;
+                }
+            }
             for (;;) {
                 // span: positions up to the lowest closing event (all if none)
                 const unsigned long long rb1 = remb - 1ull;
@@ -488,13 +502,10 @@ template <int N, bool EXACT, int D> struct MainRun {
                 unsigned long long gp = ml & upto;
                 ml &= ~upto;
                 int cpos = -1, ct = 0;
-                int lim = 0;
-                if constexpr (EXACT) {
-                    // list N-2 is fixed within the span; a lane whose windows
-                    // all end before the block's first tick cannot complete
-                    lim = m.end_of(N - 2);
-                    if (lim < tk0) gp = 0;
-                }
+                // list N-2 is fixed within the span; a lane whose list passes
+                // no tick from the block's first on cannot complete
+                const int lim = m.end_of(N - 2);
+                if (lim < tk0) gp = 0;
                 if (hx) {
                     // type ids below 64: every position in gp holds the last type
                     if constexpr (EXACT) {

@@ -107,6 +107,26 @@ def test_crowded_prefix_blocks(ctx, fe):
     _check(ctx, fe, ids_h, ticks_h, 32, cand, "crowded")
 
 
+@pytest.mark.parametrize("N,prefixes", [
+    (3, [(2, 2), (2, 5), (5, 2)]),
+    (4, [(1, 2, 2), (2, 2, 2), (2, 2, 1), (1, 2, 1)]),
+    (5, [(1, 1, 2, 2), (2, 1, 2, 1)]),
+])
+def test_repeated_prefix_types(ctx, fe, N, prefixes):
+    # node N-3 and node N-2 share a type, or node N-2's type recurs earlier:
+    # an event can both close a span and be the block's first node N-3 event;
+    # dense prefix types keep list N-3 alive across some block starts and
+    # not others
+    rng = np.random.default_rng(300 + N)
+    w = np.full(24, 1.0)
+    w[[1, 2, 5]] = 12.0
+    ids_h, ticks_h = _stream(rng, 40_000, 24, w / w.sum(), mean_gap=12)
+    cand = _prefix_runs(rng, N, 4 * len(prefixes), prefixes, np.arange(24),
+                        ivs=[(0, 50), (50, 100), (100, 200), (20, 60)])
+    banner("repeated prefix types: N=%d, %d candidates" % (N, cand["M"]))
+    _check(ctx, fe, ids_h, ticks_h, 24, cand, "repeated N=%d" % N)
+
+
 def test_mixed_waves_and_ragged_streams(ctx, fe):
     # random candidates (no shared prefix: lane-by-lane dispatch) next to
     # shared-prefix runs, over streams of every length class around a block
