@@ -24,11 +24,11 @@
 //    deadline s_k + hi_k; the hop test is t <= deadline (gap in [0, hi]).
 //  * Exact (Algorithm 1): a list matters only through the set of ticks that
 //    pass its hop test, the union over entries e of [e+lo+1, e+hi].  Each
-//    list is held as that union: sorted disjoint integer windows; windows
-//    that ended before t are dropped, touching windows merged.  Live
-//    entries lie in [t-hi, t] and unmerged neighbours are more than hi-lo
-//    apart, so at most hi/(hi-lo+1)+1 windows are live; D is that bound,
-//    fixed per candidate group at compile time.
+//    list is held as that union: disjoint integer windows in push order,
+//    touching windows merged, the D most recent kept (older ones ended
+//    before t).  Live entries lie in [t-hi, t] and unmerged neighbours are
+//    more than hi-lo apart, so at most hi/(hi-lo+1)+1 windows are live; D
+//    is that bound, fixed per candidate group at compile time.
 //
 // Exact stitching of segments: after a completion the machine is empty,
 // every occurrence spans at most W = sum(hi) ticks, and completions happen
@@ -51,8 +51,8 @@
 namespace fe {
 
 typedef const __attribute__((address_space(4))) int *cptr;
-static constexpr int EMPTY = 0x7fffffff;  // an unused window slot (after the live ones)
-static constexpr int GONE = -0x7fffffff - 1;  // end of a window dropped by a reset
+static constexpr int EMPTY = 0x7fffffff;  // start of a window slot never used
+static constexpr int GONE = -0x7fffffff - 1;  // end of an unused or cleared window slot
 static constexpr int QREC = 4;  // slot-0 completions remembered for merging
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -168,6 +168,11 @@ template <int N> struct Relaxed {
 };
 
 template <int N, int D> struct Exact {
+    // List k holds its D most recent windows in push order, slot D-1 the
+    // newest: every window of a list has the same length and starts no
+    // earlier than the ones before it, so windows end in slot order and a
+    // window's successors are live whenever it is.  An unused slot ends at
+    // GONE, before every tick.
     int wa[N > 1 ? N - 1 : 1][D];
     int wb[N > 1 ? N - 1 : 1][D];
     __device__ __forceinline__ Exact()
@@ -177,8 +182,7 @@ template <int N, int D> struct Exact {
 #pragma unroll
             for (int d = 0; d < D; ++d) { wa[k][d] = EMPTY; wb[k][d] = GONE; }
     }
-    // Empty lists: every window ends before any tick, so each is dropped as
-    // expired by the next push and no hop test passes.
+    // Empty lists: every window ends before any tick, so no hop test passes.
     __device__ __forceinline__ void reset()
     {
 #pragma unroll
@@ -195,77 +199,22 @@ template <int N, int D> struct Exact {
     }
     // Latest tick a window of list k covers (GONE when the list is empty):
     // no later tick can pass that list's test.
-    __device__ __forceinline__ int end_of(int k) const
-    {
-        int r = GONE;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const int w = (D > 2 && wb[k][d] == EMPTY) ? GONE : wb[k][d];
-            r = w > r ? w : r;
-        }
-        return r;
-    }
+    __device__ __forceinline__ int end_of(int k) const { return wb[k][D - 1]; }
+    // Window (t+lo, t+hi] joins the newest window when it overlaps or abuts
+    // it, else it becomes the newest and the oldest is shifted out; that one
+    // must have ended before t (at most D live windows, by the depth class).
     __device__ __forceinline__ void push(int k, int t, int lo, int hi, int *status)
     {
         const int a = t + lo + 1, b = t + hi;
-        // (D = 1 and 2: an unused slot has end GONE, so "ended before t" and
-        // "unused" are one test; lane masks are combined bitwise, without
-        // divergent control flow)
-        if constexpr (D == 1) {
-            // one live window at most: start anew, extend, or (invariant) fail
-            const bool gone = wb[k][0] < t;
-            const bool mrg = !gone & (wb[k][0] >= a - 1);
-            if (!gone & !mrg) atomicOr(status, ST_INTERNAL);
-            wa[k][0] = mrg ? wa[k][0] : a;
-            wb[k][0] = b;
-            return;
-        } else if constexpr (D == 2) {
-            // drop window 0 if it ended before t (window 1 then moves down;
-            // window 1 cannot end before t while window 0 lives), then
-            // extend the last live window or append after it
-            const bool x0 = wb[k][0] < t;
-            const int c0a = x0 ? wa[k][1] : wa[k][0], c0b = x0 ? wb[k][1] : wb[k][0];
-            const int c1a = wa[k][1], c1b = x0 ? GONE : wb[k][1];
-            const bool gone = c0b < t;  // no live window left
-            const bool two = c1b >= t;  // two live windows
-            const bool mrg = (two & (c1b >= a - 1)) | (!two & !gone & (c0b >= a - 1));
-            if (two & !mrg) atomicOr(status, ST_INTERNAL);
-            wa[k][0] = gone ? a : c0a;
-            wb[k][0] = gone ? b : ((!two & mrg) ? b : c0b);
-            wa[k][1] = two ? c1a : a;
-            wb[k][1] = gone ? GONE : (two ? (mrg ? b : c1b) : (mrg ? GONE : b));
-            return;
+        const bool mrg = wb[k][D - 1] >= a - 1;
+        if (!mrg & (wb[k][0] >= t)) atomicOr(status, ST_INTERNAL);
+#pragma unroll
+        for (int d = 0; d + 1 < D; ++d) {
+            wa[k][d] = mrg ? wa[k][d] : wa[k][d + 1];
+            wb[k][d] = mrg ? wb[k][d] : wb[k][d + 1];
         }
-        int nd = 0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) nd += wb[k][d] < t ? 1 : 0;
-        int na[D], nb[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            na[d] = EMPTY;
-            nb[d] = EMPTY;
-#pragma unroll
-            for (int s = 0; s + d < D; ++s)
-                if (s == nd) { na[d] = wa[k][d + s]; nb[d] = wb[k][d + s]; }
-        }
-        int lc = 0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) lc += nb[d] != EMPTY ? 1 : 0;
-        bool merged = false;
-#pragma unroll
-        for (int d = 0; d < D; ++d)
-            if (d == lc - 1 && nb[d] >= a - 1) { nb[d] = b; merged = true; }
-        if (!merged) {
-            if (lc < D) {
-#pragma unroll
-                for (int d = 0; d < D; ++d)
-                    if (d == lc) { na[d] = a; nb[d] = b; }
-            } else {
-                atomicOr(status, ST_INTERNAL);
-            }
-        }
-#pragma unroll
-        for (int d = 0; d < D; ++d) { wa[k][d] = na[d]; wb[k][d] = nb[d]; }
+        wa[k][D - 1] = mrg ? wa[k][D - 1] : a;
+        wb[k][D - 1] = b;
     }
     __device__ __forceinline__ bool step(int e, int t, const Cand<N> &c, bool on, int *status)
     {
