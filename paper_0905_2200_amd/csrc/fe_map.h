@@ -419,14 +419,20 @@ template <int N, bool EXACT, int D> struct MainRun {
         const EvBuf eb(ids, ticks, cb, ce);
         int nid, ntk;
         eb.load(0, lane4, nid, ntk);
-        for (int i = cb; i < ce; i += WAVE) {
+        // (full blocks and the final partial one are separate copies of the
+        // body, so that full blocks need no position mask)
+        auto block = [&](auto full_tag, int i) {
+            constexpr bool FULL = decltype(full_tag)::value;
             const int id = nid, tk = ntk;
             eb.load(i - cb + WAVE, lane4, nid, ntk);
-            const bool v = lane < ce - i;
+            const int left = ce - i;
+            const bool v = FULL || lane < left;
+            // positions holding events of this block (a wave-uniform mask)
+            const unsigned long long vm = FULL ? ~0ull : (1ull << left) - 1ull;
             const int h = id & 63;
             const unsigned long long pm =
-                __builtin_amdgcn_ballot_w64(v & (((u.mask >> h) & 1ull) != 0));
-            const unsigned long long bm = __builtin_amdgcn_ballot_w64(v & (h == bh));
+                __builtin_amdgcn_ballot_w64(((u.mask >> h) & 1ull) != 0) & vm;
+            const unsigned long long bm = __builtin_amdgcn_ballot_w64(h == bh) & vm;
             tm[lane] = 0;
             evs[lane] = make_int2(id, tk);
             if (v) atomicOr(&tm[h], 1ull << lane);
@@ -440,8 +446,10 @@ template <int N, bool EXACT, int D> struct MainRun {
                 // the block, so the events before the first node N-3 event
                 // close no span.
                 if (__builtin_amdgcn_ballot_w64(m.end_of(N - 3) >= tk0) == 0) {
-                    const unsigned long long am = __builtin_amdgcn_ballot_w64(v & (h == ah));
-                    remb = am ? (bm & ~(((am & (0ull - am)) << 1) - 1ull)) : 0ull;
+                    const unsigned long long am = __builtin_amdgcn_ballot_w64(h == ah) & vm;
+                    // (am ^ (am - 1): positions up to the first such event;
+                    // all of them when there is none)
+                    remb = bm & ~(am ^ (am - 1ull));
                 }
             }
             for (;;) {
@@ -527,7 +535,10 @@ template <int N, bool EXACT, int D> struct MainRun {
                 if (!remb) break;
                 remb &= rb1;
             }
-        }
+        };
+        int i = cb;
+        for (; i + WAVE <= ce; i += WAVE) block(std::true_type(), i);
+        if (i < ce) block(std::false_type(), i);
         }
     }
 
