@@ -399,10 +399,18 @@ template <int N, bool EXACT, int D> struct MainRun {
     // span's end.  Then the span's prefix events push in order, except, in
     // that lane, those at or before its completion.  tm, evs: this wave's
     // 64-entry LDS scratch.
+    // hx: every type id is below 64 (each instantiation has one hot loop)
     template <bool NOTE>
     __device__ void sparse(const int *ids, const int *ticks, int b, int e, const Cand<N> &c,
                            const Prefix<N> &u, unsigned long long *tm, int2 *evs, int *status,
                            bool hx)
+    {
+        if (hx) sparse_t<NOTE, true>(ids, ticks, b, e, c, u, tm, evs, status);
+        else sparse_t<NOTE, false>(ids, ticks, b, e, c, u, tm, evs, status);
+    }
+    template <bool NOTE, bool HX>
+    __device__ void sparse_t(const int *ids, const int *ticks, int b, int e, const Cand<N> &c,
+                             const Prefix<N> &u, unsigned long long *tm, int2 *evs, int *status)
     {
         static_assert(N >= 2, "per-type dispatch needs a shared prefix");
         b = uniform(b);
@@ -463,7 +471,7 @@ template <int N, bool EXACT, int D> struct MainRun {
                 // no tick from the block's first on cannot complete
                 const int lim = m.end_of(N - 2);
                 if (lim < tk0) gp = 0;
-                if (hx) {
+                if constexpr (HX) {
                     // type ids below 64: every position in gp holds the last type
                     if constexpr (EXACT) {
                         while (gp) {
