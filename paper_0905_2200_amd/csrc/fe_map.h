@@ -154,8 +154,9 @@ template <int N> struct Relaxed {
     }
     // Nodes 0..N-2 of a shared-prefix wave only (the last node's test is
     // taken elsewhere); lanes with on = false leave their lists as they are.
+    // (lm, hm: unused; the relaxed hop test is as cheap as a bound test)
     __device__ __forceinline__ void push_u(int e, int t, const Cand<N> &c, const Prefix<N> &u,
-                                           bool on, int *)
+                                           bool on, int *, int *, const int *)
     {
         if constexpr (N > 1) {
 #pragma unroll
@@ -253,16 +254,24 @@ template <int N, int D> struct Exact {
     }
     // Nodes 0..N-2 of a shared-prefix wave only (the last node's test is
     // taken elsewhere); lanes with on = false leave their lists as they are.
+    // lm[k]: a wave-uniform bound on every lane's end_of(k); hm[k]: the
+    // wave's largest hi of hop k.  A node whose list k-1 passes at no lane
+    // (t > lm[k-1]) is skipped whole.
     __device__ __forceinline__ void push_u(int e, int t, const Cand<N> &c, const Prefix<N> &u,
-                                           bool on, int *status)
+                                           bool on, int *status, int *lm, const int *hm)
     {
         if constexpr (N > 1) {
 #pragma unroll
             for (int i = N - 2; i >= 1; --i)
                 if (__builtin_expect(e == u.ty[i], 0))
-                    if (on & hit(i - 1, t)) push(i, t, c.lo[i], c.hi[i], status);
-            if (__builtin_expect(e == u.ty[0], 0))
+                    if (t <= lm[i - 1]) {
+                        lm[i] = t + hm[i];
+                        if (on & hit(i - 1, t)) push(i, t, c.lo[i], c.hi[i], status);
+                    }
+            if (__builtin_expect(e == u.ty[0], 0)) {
+                lm[0] = t + hm[0];
                 if (on) push(0, t, c.lo[0], c.hi[0], status);
+            }
         }
     }
 };
@@ -422,6 +431,24 @@ template <int N, bool EXACT, int D> struct MainRun {
         const int bh = u.ty[N - 2] & 63;
         const int ah = u.ty[N >= 3 ? N - 3 : 0] & 63;
         const int lane4 = lane * 4;
+        // wave-uniform bounds: hm[k] the largest hi of hop k, lm[k] >= every
+        // lane's end_of(k) (raised at each node k event that may push)
+        int hm[N - 1], lm[N - 1];
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) {
+            hm[k] = 0;
+            lm[k] = 0;
+            if constexpr (!EXACT) continue;
+            int x = c.hi[k], y = m.end_of(k);
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const int ox = __shfl_xor(x, off), oy = __shfl_xor(y, off);
+                x = ox > x ? ox : x;
+                y = oy > y ? oy : y;
+            }
+            hm[k] = uniform(x);
+            lm[k] = uniform(y);
+        }
         for (int cb = b; cb < e; cb += EV_CHUNK) {
         const int ce = e - cb > EV_CHUNK ? cb + EV_CHUNK : e;
         const EvBuf eb(ids, ticks, cb, ce);
@@ -453,7 +480,9 @@ template <int N, bool EXACT, int D> struct MainRun {
                 // block's first tick, that needs a node N-3 push earlier in
                 // the block, so the events before the first node N-3 event
                 // close no span.
-                if (__builtin_amdgcn_ballot_w64(m.end_of(N - 3) >= tk0) == 0) {
+                const bool none = EXACT ? lm[N - 3] < tk0
+                                        : __builtin_amdgcn_ballot_w64(m.end_of(N - 3) >= tk0) == 0;
+                if (none) {
                     const unsigned long long am = __builtin_amdgcn_ballot_w64(h == ah) & vm;
                     // (am ^ (am - 1): positions up to the first such event;
                     // all of them when there is none)
@@ -464,13 +493,17 @@ template <int N, bool EXACT, int D> struct MainRun {
                 // span: positions up to the lowest closing event (all if none)
                 const unsigned long long rb1 = remb - 1ull;
                 const unsigned long long upto = remb ? (remb ^ rb1) : ~0ull;
-                unsigned long long gp = ml & upto;
-                ml &= ~upto;
-                int cpos = -1, ct = 0;
                 // list N-2 is fixed within the span; a lane whose list passes
                 // no tick from the block's first on cannot complete
-                const int lim = m.end_of(N - 2);
-                if (lim < tk0) gp = 0;
+                unsigned long long gp = 0;
+                int lim = GONE;
+                if (!EXACT || lm[N - 2] >= tk0) {
+                    gp = ml & upto;
+                    lim = m.end_of(N - 2);
+                    if (lim < tk0) gp = 0;
+                }
+                ml &= ~upto;
+                int cpos = -1, ct = 0;
                 if constexpr (HX) {
                     // type ids below 64: every position in gp holds the last type
                     if constexpr (EXACT) {
@@ -538,7 +571,7 @@ template <int N, bool EXACT, int D> struct MainRun {
                     pp &= pp - 1ull;
                     const int ev = __builtin_amdgcn_readlane(id, x);
                     const int t = __builtin_amdgcn_readlane(tk, x);
-                    m.push_u(ev, t, c, u, x > cpos, status);
+                    m.push_u(ev, t, c, u, x > cpos, status, lm, hm);
                 }
                 if (!remb) break;
                 remb &= rb1;
