@@ -101,12 +101,18 @@ typedef enum fe_param {
                                 6926: fitted to crossovers measured on a 256-CU
                                 MI355X (python -m paper_0905_2200_amd.crossover).
                                 Ignored when FE_PARAM_SEGMENTS > 0.           */
-    FE_PARAM_ELIMINATION = 8  /* fe_mine: 1 (default) = two-pass elimination
+    FE_PARAM_ELIMINATION = 8, /* fe_mine: 1 (default) = two-pass elimination
                                 (Algorithm 4: relaxed pass, prune, exact pass
                                 on the survivors); 0 = one pass of Algorithm 1
                                 over every candidate (upper reported as -1).
                                 The frequent episodes and exact counts are the
                                 same either way.                              */
+    FE_PARAM_HOST_TILING = 9  /* fe_mine: 0 = each level's candidates are
+                                pruned and tiled on the device (sibling runs
+                                whole, by list-depth class); 1 (default) = the
+                                same tiling on the host (the relaxed counts
+                                are copied back and the lane assignment
+                                uploaded).  Same tiles, same results.         */
 } fe_param;
 
 typedef struct fe_ctx fe_ctx;

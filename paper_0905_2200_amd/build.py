@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfe.so")
-SOURCES = ["fe_kernels.hip", "fe_host.hip"] + ["fe_map_n%d.hip" % n for n in range(1, 9)]
+SOURCES = ["fe_kernels.hip", "fe_tiling.hip", "fe_host.hip"] + ["fe_map_n%d.hip" % n for n in range(1, 9)]
 ARCH = os.environ.get("FE_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -95,11 +95,11 @@ struct fe_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
-    int64_t param[9] = {0, 4096, 1024, 1, 0, 1, 24200, 6926, 1};
+    int64_t param[10] = {0, 4096, 1024, 1, 0, 1, 24200, 6926, 1, 1};
     fe_stats stats{};
     // workspace
     Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
-    Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn, mkey;
+    Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn, mkey, tscr, tinfo;
     // host arrays of the mining driver, kept for reuse (large ones are pinned)
     ivec keypool, lanepool, uphpool, orderpool;
     int *host = nullptr;  // pinned host staging for small readbacks
@@ -626,7 +626,7 @@ extern "C" int fe_destroy(fe_ctx *c)
     Buf *bufs[] = {&c->keys, &c->hist, &c->wmax, &c->fill, &c->pk,    &c->orig,  &c->tileW,
                    &c->lam,  &c->tbl,  &c->flags, &c->sel, &c->nsel,  &c->status, &c->small, &c->cmask,
                    &c->mtypes, &c->mlen, &c->mlo, &c->mhi, &c->mup, &c->mex, &c->msel, &c->mn,
-                   &c->mkey};
+                   &c->mkey, &c->tscr, &c->tinfo};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &p : c->pending) {
@@ -665,7 +665,7 @@ extern "C" int fe_sync(fe_ctx *c)
 extern "C" int fe_set_param(fe_ctx *c, int param, int64_t value)
 {
     if (!c) return FE_EINVAL;
-    if (param < 0 || param > 8 || value < 0) return fail(c, FE_EINVAL, "bad parameter");
+    if (param < 0 || param > 9 || value < 0) return fail(c, FE_EINVAL, "bad parameter");
     if (param == FE_PARAM_TARGET_WAVES && value == 0) return fail(c, FE_EINVAL, "bad parameter");
     c->param[param] = value;
     return FE_OK;
@@ -673,7 +673,7 @@ extern "C" int fe_set_param(fe_ctx *c, int param, int64_t value)
 
 extern "C" int fe_get_param(const fe_ctx *c, int param, int64_t *value)
 {
-    if (!c || !value || param < 0 || param > 8) return FE_EINVAL;
+    if (!c || !value || param < 0 || param > 9) return FE_EINVAL;
     *value = c->param[param];
     return FE_OK;
 }
@@ -1195,6 +1195,52 @@ int upload_pack(fe_ctx *c, const HostPack &hp)
     return FE_OK;
 }
 
+// Device tiling of a level (fe_tiling.hip): lanes, records and look-back
+// widths of the candidates kept (all, or upper >= theta when up is set),
+// grouped by list-depth class when exact.  kept: their number.
+int dev_pack(fe_ctx *c, const int *key_d, int m, int64_t M, const int *up, int theta,
+             bool exact, int wbound, std::vector<GroupDesc> &groups, int64_t &kept)
+{
+    int rc;
+    hipStream_t s = c->stream;
+    groups.clear();
+    kept = 0;
+    constexpr int NINFO = 5 * NDCLS + 1;
+    if ((rc = ensure(c, c->tscr, (size_t)tile_scratch_ints(M) * sizeof(int)))) return rc;
+    if ((rc = ensure(c, c->tinfo, NINFO * sizeof(int)))) return rc;
+    if ((rc = ensure_host(c, NINFO))) return rc;
+    {
+        KTimer kt(c, "tile_plan", 0);
+        launch_tile_plan(key_d, m, M, up, theta, exact, P<int>(c->tscr), P<int>(c->tinfo), s);
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->host, P<int>(c->tinfo), NINFO * sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    int info[NINFO];
+    std::memcpy(info, c->host, sizeof info);
+    const int64_t tiles = info[5 * NDCLS];
+    for (int k = 0; k < NDCLS; ++k) kept += info[4 * NDCLS + k];
+    if (tiles == 0) return FE_OK;
+    const int ri = rec_ints(m);
+    if ((rc = ensure(c, c->pk, (size_t)tiles * ri * sizeof(int)))) return rc;
+    if ((rc = ensure(c, c->orig, (size_t)tiles * WAVE * sizeof(int)))) return rc;
+    if ((rc = ensure(c, c->tileW, (size_t)tiles * sizeof(int)))) return rc;
+    launch_fill(P<int>(c->orig), -1, tiles * WAVE, s);
+    {
+        KTimer kt(c, "tile_lanes", 0);
+        launch_tile_lanes(M, P<int>(c->tscr), P<int>(c->tinfo), P<int>(c->orig), s);
+    }
+    launch_build_rec(key_d, m, P<int>(c->orig), (int)tiles, P<int>(c->pk), P<int>(c->tileW), s);
+    HIPCHK(c, hipGetLastError());
+    for (int k = 0; k < NDCLS; ++k)
+        if (info[k] > 0)
+            groups.push_back(GroupDesc{(m - 1) * NDCLS + k, info[k], info[NDCLS + k],
+                                       (int64_t)info[NDCLS + k] * ri, wbound,
+                                       (int64_t)info[4 * NDCLS + k]});
+    return FE_OK;
+}
+
 }  // namespace
 
 extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int64_t n,
@@ -1285,7 +1331,27 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         HostPack hp;
         ivec order;
         const bool elim = c->param[FE_PARAM_ELIMINATION] != 0;
-        if (elim) {
+        const bool htile = c->param[FE_PARAM_HOST_TILING] != 0;
+        int64_t kept = 0;  // candidates of the exact pass (device tiling)
+        if (!htile) {
+            // prune and tile on the device: pass 1 (Algorithm 3) over every
+            // candidate, then pass 2 (Algorithm 1) over those with
+            // upper >= theta (Algorithm 4), or over all in one-pass mode
+            std::vector<GroupDesc> groups;
+            if (elim) {
+                if ((rc = dev_pack(c, P<int>(c->mkey), level, (int64_t)M, nullptr, 0, false,
+                                   wbound, groups, kept)))
+                    return rc;
+                if ((rc = launch_groups(c, ids, ticks, si, groups, false, up))) return rc;
+            } else {
+                launch_fill(up, -1, (int64_t)M, s);
+            }
+            launch_fill(ex, -1, (int64_t)M, s);
+            if ((rc = dev_pack(c, P<int>(c->mkey), level, (int64_t)M, elim ? up : nullptr, theta,
+                               true, wbound, groups, kept)))
+                return rc;
+            if (kept > 0 && (rc = launch_groups(c, ids, ticks, si, groups, true, ex))) return rc;
+        } else if (elim) {
             // pass 1 (Algorithm 3) over every candidate
             {
                 HTimer ht(c, "host_pack");
@@ -1315,10 +1381,10 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
             // one pass: Algorithm 1 over every candidate, no relaxed count
             launch_fill(up, -1, (int64_t)M, s);
         }
-        const int64_t nsurv = elim ? (int64_t)order.size() : (int64_t)M;
+        const int64_t nsurv = !htile ? kept : elim ? (int64_t)order.size() : (int64_t)M;
         // pass 2 (Algorithm 1) over the survivors; the others keep -1
-        launch_fill(ex, -1, (int64_t)M, s);
-        if (nsurv > 0) {
+        if (htile) launch_fill(ex, -1, (int64_t)M, s);
+        if (htile && nsurv > 0) {
             {
                 HTimer ht(c, "host_pack");
                 host_pack(C, elim ? order.data() : nullptr, nsurv, true, hp, wbound,

@@ -106,6 +106,13 @@ void launch_resume(int N, bool exact, int dcls, const MapGroup &g, int from, int
                    int *last_io, hipStream_t s);
 void launch_build_rec(const int *key, int m, const int *orig, int tiles, int *rec, int *tileW,
                       hipStream_t s);
+// Run-aligned tiling of a level on the device (fe_tiling.hip).  scratch:
+// tile_scratch_ints(M) ints; info: 5*NDCLS+1 ints (per class: tiles, first
+// tile, run tiles, first run, candidates; then the total tiles).
+int64_t tile_scratch_ints(int64_t M);
+void launch_tile_plan(const int *key, int m, int64_t M, const int *up, int theta, bool exact,
+                      int *scratch, int *info, hipStream_t s);
+void launch_tile_lanes(int64_t M, const int *scratch, const int *info, int *orig, hipStream_t s);
 void launch_persist_fixup(int N, bool exact, int dcls, const BatchDev &b, const int *ctiles,
                           int nct, hipStream_t s);
 void launch_plan_batch(const TileDesc *tiles, const BJob *jobs, const int *tileW,

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "libfe.so")
 FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_EUNSORTED, FE_ERANGE, FE_EBUSY, FE_EINTERNAL = range(8)
 FE_EXACT, FE_RELAXED = 0, 1
 PARAM_SEGMENTS, PARAM_TARGET_WAVES, PARAM_MIN_SEG_EVENTS, PARAM_CONCAT_TREE, PARAM_TIMING, \
-    PARAM_TYPE_DISPATCH, PARAM_CROSSOVER_A, PARAM_CROSSOVER_B, PARAM_ELIMINATION = range(9)
+    PARAM_TYPE_DISPATCH, PARAM_CROSSOVER_A, PARAM_CROSSOVER_B, PARAM_ELIMINATION, \
+    PARAM_HOST_TILING = range(10)
 
 STATUS_NAMES = {0: "FE_OK", 1: "FE_EINVAL", 2: "FE_ENOMEM", 3: "FE_EDEVICE",
                 4: "FE_EUNSORTED", 5: "FE_ERANGE", 6: "FE_EBUSY", 7: "FE_EINTERNAL"}

@@ -214,3 +214,49 @@ def test_one_pass_mining_same_result(ctx, fe):
         if a["level"] >= 2:
             assert (np.asarray(b["upper"]) == -1).all()
             assert b["n_survivors"] == b["n_candidates"]
+
+
+def _mine_with(ctx, fe, s, intervals, theta, max_level, htile, elim):
+    ids, ticks = ctx.stream_tensors(s["ids"], s["ticks"])
+    h0 = ctx.get_param(fe.PARAM_HOST_TILING)
+    ctx.set_param(fe.PARAM_HOST_TILING, htile)
+    ctx.set_param(fe.PARAM_ELIMINATION, elim)
+    try:
+        return ctx.mine(ids, ticks, s["num_types"], intervals, theta, max_level)
+    finally:
+        ctx.set_param(fe.PARAM_HOST_TILING, h0)
+        ctx.set_param(fe.PARAM_ELIMINATION, 1)
+
+
+def _same_levels(a, b):
+    assert len(a) == len(b)
+    for x, y in zip(a, b):
+        for k in ("level", "n_candidates", "n_survivors", "n_frequent"):
+            assert x[k] == y[k], (x["level"], k, x[k], y[k])
+        for k in ("types", "lo", "hi", "upper", "exact"):
+            assert np.array_equal(np.asarray(x[k]), np.asarray(y[k])), (x["level"], k)
+
+
+@pytest.mark.parametrize("elim", [1, 0])
+def test_device_tiling_same_as_host(ctx, fe, elim):
+    # pruning and tiling on the device (default) against the host tiler:
+    # the same survivors, frequent episodes and counts at every level
+    s = synth.config_mining(duration_s=60.0)
+    banner("device vs host tiling, mining 60 s, elimination=%d" % elim)
+    dev = _mine_with(ctx, fe, s, s["intervals"], s["theta"], 5, 0, elim)
+    host = _mine_with(ctx, fe, s, s["intervals"], s["theta"], 5, 1, elim)
+    _same_levels(dev, host)
+    assert any(L["n_frequent"] > 0 for L in dev if L["level"] >= 3)
+
+
+def test_device_tiling_depth_classes(ctx, fe):
+    # intervals of list-depth classes 0, 1 and 2 in one level, a low threshold
+    # (most candidates frequent, so a lost or doubled lane would show), and
+    # short sibling runs (16 types): full, padded and packed tiles per class
+    s = synth.config_mining(n_neurons=16, duration_s=40.0)
+    ivs = [(0, 50), (50, 100), (100, 150), (20, 30)]
+    banner("device vs host tiling, depth classes, n=%d" % s["ids"].size)
+    dev = _mine_with(ctx, fe, s, ivs, 10, 4, 0, 1)
+    host = _mine_with(ctx, fe, s, ivs, 10, 4, 1, 1)
+    _same_levels(dev, host)
+    assert dev[-1]["level"] == 4 and dev[-1]["n_frequent"] > 1000
