@@ -139,6 +139,9 @@ def main():
                     help="streaming: seconds of recording per partition")
     ap.add_argument("--one-pass", action="store_true",
                     help="mining: Algorithm 1 over every candidate, no elimination pass")
+    ap.add_argument("--host-tiling", type=int, default=None, choices=[0, 1],
+                    help="mining: 1 = tile each level on the host, 0 = on the device "
+                         "(default: the library's)")
     ap.add_argument("--type-dispatch", type=int, default=1, choices=[0, 1],
                     help="per-type dispatch for shared-prefix waves (0 = every event)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -175,6 +178,8 @@ def main():
     ctx = fe.Context(0)
     ctx.set_param(fe.PARAM_TYPE_DISPATCH, args.type_dispatch)
     ctx.set_param(fe.PARAM_ELIMINATION, 0 if args.one_pass else 1)
+    if args.host_tiling is not None:
+        ctx.set_param(fe.PARAM_HOST_TILING, args.host_tiling)
     ids, ticks = ctx.stream_tensors(s["ids"], s["ticks"])
     torch.cuda.synchronize()
 

@@ -107,11 +107,11 @@ typedef enum fe_param {
                                 over every candidate (upper reported as -1).
                                 The frequent episodes and exact counts are the
                                 same either way.                              */
-    FE_PARAM_HOST_TILING = 9  /* fe_mine: 0 = each level's candidates are
-                                pruned and tiled on the device (sibling runs
-                                whole, by list-depth class); 1 (default) = the
-                                same tiling on the host (the relaxed counts
-                                are copied back and the lane assignment
+    FE_PARAM_HOST_TILING = 9  /* fe_mine: 0 (default) = each level's
+                                candidates are pruned and tiled on the device
+                                (sibling runs whole, by list-depth class);
+                                1 = the same tiling on the host (the relaxed
+                                counts are copied back and the lane assignment
                                 uploaded).  Same tiles, same results.         */
 } fe_param;
 

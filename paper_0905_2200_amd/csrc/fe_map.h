@@ -154,23 +154,16 @@ template <int N> struct Relaxed {
     }
     // Nodes 0..N-2 of a shared-prefix wave only (the last node's test is
     // taken elsewhere); lanes with on = false leave their lists as they are.
-    // lm[N-2]: a wave-uniform bound on every lane's dl[N-2], raised at each
-    // node N-2 event by hm[N-2], the wave's largest hi of that hop (the other
-    // hop tests are as cheap as a bound test, so they keep no bound)
+    // (lm, hm: unused; the relaxed hop test is as cheap as a bound test)
     __device__ __forceinline__ void push_u(int e, int t, const Cand<N> &c, const Prefix<N> &u,
-                                           bool on, int *, int *lm, const int *hm)
+                                           bool on, int *, int *, const int *)
     {
         if constexpr (N > 1) {
 #pragma unroll
             for (int i = N - 2; i >= 1; --i)
-                if (__builtin_expect(e == u.ty[i], 0)) {
-                    if (i == N - 2) lm[i] = t + hm[i];
+                if (__builtin_expect(e == u.ty[i], 0))
                     dl[i] = (on & (t <= dl[i - 1])) ? t + c.hi[i] : dl[i];
-                }
-            if (__builtin_expect(e == u.ty[0], 0)) {
-                if (N == 2) lm[0] = t + hm[0];
-                dl[0] = on ? t + c.hi[0] : dl[0];
-            }
+            if (__builtin_expect(e == u.ty[0], 0)) dl[0] = on ? t + c.hi[0] : dl[0];
         }
     }
 };
@@ -445,7 +438,7 @@ template <int N, bool EXACT, int D> struct MainRun {
         for (int k = 0; k < N - 1; ++k) {
             hm[k] = 0;
             lm[k] = 0;
-            if (!EXACT && k != N - 2) continue;
+            if constexpr (!EXACT) continue;
             int x = c.hi[k], y = m.end_of(k);
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) {
@@ -504,7 +497,7 @@ template <int N, bool EXACT, int D> struct MainRun {
                 // no tick from the block's first on cannot complete
                 unsigned long long gp = 0;
                 int lim = GONE;
-                if (lm[N - 2] >= tk0) {
+                if (!EXACT || lm[N - 2] >= tk0) {
                     gp = ml & upto;
                     lim = m.end_of(N - 2);
                     if (lim < tk0) gp = 0;
