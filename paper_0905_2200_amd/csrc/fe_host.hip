@@ -99,7 +99,7 @@ struct fe_ctx {
     fe_stats stats{};
     // workspace
     Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
-    Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn, mkey, tscr, tinfo;
+    Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn, mkey, tscr, tinfo, mfk, mfo, mfsel;
     // host arrays of the mining driver, kept for reuse (large ones are pinned)
     ivec keypool, lanepool, uphpool, orderpool;
     int *host = nullptr;  // pinned host staging for small readbacks
@@ -626,7 +626,7 @@ extern "C" int fe_destroy(fe_ctx *c)
     Buf *bufs[] = {&c->keys, &c->hist, &c->wmax, &c->fill, &c->pk,    &c->orig,  &c->tileW,
                    &c->lam,  &c->tbl,  &c->flags, &c->sel, &c->nsel,  &c->status, &c->small, &c->cmask,
                    &c->mtypes, &c->mlen, &c->mlo, &c->mhi, &c->mup, &c->mex, &c->msel, &c->mn,
-                   &c->mkey, &c->tscr, &c->tinfo};
+                   &c->mkey, &c->tscr, &c->tinfo, &c->mfk, &c->mfo, &c->mfsel};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &p : c->pending) {
@@ -920,12 +920,15 @@ void gen_level2(const std::vector<int> &F1, const std::vector<int> &ilo,
 // beta whose first m-1 nodes and intervals equal alpha's last m-1, in the
 // order (alpha, beta).  Each alpha's betas are one contiguous range of F;
 // ranges are found and written in parallel.
-void gen_join(const Episodes &F, Episodes &out)
+// Range search of the join: for each alpha of F (sorted), first[a] = the
+// first beta whose first m-1 nodes and hops equal alpha's last m-1, and
+// alpha's candidates are outputs off[a]..off[a+1]; returns off[cnt].
+int64_t gen_join_plan(const Episodes &F, std::vector<int64_t> &first, std::vector<int64_t> &off)
 {
-    const int m = F.m, w = 3 * m - 2, ov = 3 * m - 5, wo = w + 3;
-    out.m = m + 1;
+    const int m = F.m, ov = 3 * m - 5;
     const int64_t cnt = (int64_t)F.count();
-    std::vector<int64_t> first(cnt), off(cnt + 1, 0);
+    first.assign(cnt, 0);
+    off.assign(cnt + 1, 0);
     par_for(cnt, 4096, [&](int64_t b, int64_t e, int) {
         for (int64_t a = b; a < e; ++a) {
             const int *suf = F.at(a) + 3;
@@ -950,6 +953,16 @@ void gen_join(const Episodes &F, Episodes &out)
         }
     });
     for (int64_t a = 0; a < cnt; ++a) off[a + 1] += off[a];
+    return off[cnt];
+}
+
+void gen_join(const Episodes &F, Episodes &out)
+{
+    const int m = F.m, w = 3 * m - 2, wo = w + 3;
+    out.m = m + 1;
+    const int64_t cnt = (int64_t)F.count();
+    std::vector<int64_t> first, off;
+    gen_join_plan(F, first, off);
     out.key.resize((size_t)off[cnt] * wo);
     par_for(cnt, 4096, [&](int64_t b, int64_t e, int) {
         for (int64_t a = b; a < e; ++a) {
@@ -1301,14 +1314,21 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
 
     for (int level = 2; level <= max_level && F.count() > 0 && n_iv > 0; ++level) {
         t0 = now_ms();
+        const bool htile = c->param[FE_PARAM_HOST_TILING] != 0;
+        // level >= 3 with device tiling: the join's ranges are searched on
+        // the host and the keys written on the device (they never cross PCIe)
+        const bool djoin = !htile && level >= 3;
         Episodes C;
         C.key.swap(c->keypool);
+        std::vector<int64_t> jfirst, joff;
+        size_t M;
         {
             HTimer ht(c, "host_gen");
             if (level == 2) gen_level2(levels[0].types, ilo, ihi, C);
-            else gen_join(F, C);
+            else if (!djoin) gen_join(F, C);
+            else C.m = level;
+            M = djoin ? (size_t)gen_join_plan(F, jfirst, joff) : C.count();
         }
-        const size_t M = C.count();
         if (M == 0) break;
         if (M >= (size_t)1 << 31 || M * level >= (size_t)1 << 31)
             return fail(c, FE_ENOMEM, "level %d has too many candidates (%zu)", level, M);
@@ -1321,8 +1341,25 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         int *up = P<int>(c->mup), *ex = P<int>(c->mex);
         // the level's keys go to the device once; tile records are built there
         const int wbound = (level - 1) * *std::max_element(ihi.begin(), ihi.end());
-        if ((rc = ensure(c, c->mkey, std::max<size_t>(C.key.size(), 1) * sizeof(int)))) return rc;
-        {
+        const int wk = 3 * level - 2;  // ints per key
+        if ((rc = ensure(c, c->mkey, std::max<size_t>(M * wk, 1) * sizeof(int)))) return rc;
+        if (djoin) {
+            const int64_t cnt = (int64_t)F.count();
+            const size_t fb = F.key.size() * sizeof(int), ob = (size_t)(cnt + 1) * sizeof(int64_t);
+            if ((rc = ensure(c, c->mfk, fb))) return rc;
+            if ((rc = ensure(c, c->mfo, 2 * ob))) return rc;
+            HTimer ht(c, "host_upload");
+            HIPCHK(c, hipMemcpyAsync(c->mfk.p, F.key.data(), fb, hipMemcpyHostToDevice, s));
+            HIPCHK(c, hipMemcpyAsync(c->mfo.p, jfirst.data(), cnt * sizeof(int64_t),
+                                     hipMemcpyHostToDevice, s));
+            HIPCHK(c, hipMemcpyAsync((char *)c->mfo.p + ob, joff.data(), ob,
+                                     hipMemcpyHostToDevice, s));
+            launch_join(P<int>(c->mfk), 3 * F.m - 2, (const int64_t *)c->mfo.p,
+                        (const int64_t *)((char *)c->mfo.p + ob), cnt, (int64_t)M,
+                        P<int>(c->mkey), s);
+            HIPCHK(c, hipGetLastError());
+            // (F, jfirst and joff outlive the stream synchronisation below)
+        } else {
             // (pinned when large: the copy overlaps the host tiling below)
             HTimer ht(c, "host_upload");
             HIPCHK(c, hipMemcpyAsync(P<int>(c->mkey), C.key.data(), C.key.size() * sizeof(int),
@@ -1331,7 +1368,6 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         HostPack hp;
         ivec order;
         const bool elim = c->param[FE_PARAM_ELIMINATION] != 0;
-        const bool htile = c->param[FE_PARAM_HOST_TILING] != 0;
         int64_t kept = 0;  // candidates of the exact pass (device tiling)
         if (!htile) {
             // prune and tile on the device: pass 1 (Algorithm 3) over every
@@ -1417,10 +1453,20 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         }
         Episodes NF;
         NF.m = level;
-        NF.key.resize((size_t)nf * (3 * level - 2));
-        for (int i = 0; i < nf; ++i)
-            std::memcpy(NF.key.data() + (size_t)i * (3 * level - 2), C.at(fsel[i]),
-                        (3 * level - 2) * sizeof(int));
+        NF.key.resize((size_t)nf * wk);
+        if (djoin) {
+            // the frequent keys come back from the device
+            if (nf > 0) {
+                if ((rc = ensure(c, c->mfsel, (size_t)nf * wk * sizeof(int)))) return rc;
+                launch_gather_keys(P<int>(c->mkey), wk, P<int>(c->msel), nf, P<int>(c->mfsel), s);
+                HIPCHK(c, hipMemcpyAsync(NF.key.data(), c->mfsel.p, (size_t)nf * wk * sizeof(int),
+                                         hipMemcpyDeviceToHost, s));
+                HIPCHK(c, hipStreamSynchronize(s));
+            }
+        } else {
+            for (int i = 0; i < nf; ++i)
+                std::memcpy(NF.key.data() + (size_t)i * wk, C.at(fsel[i]), wk * sizeof(int));
+        }
         sort_episodes(NF, &fup, &fex);
         LevelOut Lv;
         Lv.level = level;

@@ -113,6 +113,11 @@ int64_t tile_scratch_ints(int64_t M);
 void launch_tile_plan(const int *key, int m, int64_t M, const int *up, int theta, bool exact,
                       int *scratch, int *info, hipStream_t s);
 void launch_tile_lanes(int64_t M, const int *scratch, const int *info, int *orig, hipStream_t s);
+// Join of sorted frequent m-node keys F into level m+1 keys (w = 3m-2;
+// first/off from the host's range search), and a gather of selected keys.
+void launch_join(const int *F, int w, const int64_t *first, const int64_t *off, int64_t cnt,
+                 int64_t M, int *out, hipStream_t s);
+void launch_gather_keys(const int *key, int w, const int *sel, int nsel, int *out, hipStream_t s);
 void launch_persist_fixup(int N, bool exact, int dcls, const BatchDev &b, const int *ctiles,
                           int nct, hipStream_t s);
 void launch_plan_batch(const TileDesc *tiles, const BJob *jobs, const int *tileW,

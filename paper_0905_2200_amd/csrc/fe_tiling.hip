@@ -1,5 +1,5 @@
-// Run-aligned tiling of a level's candidates on the device (level-wise
-// mining, both passes of Algorithm 4).
+// Level-wise mining on the device: candidate generation by the join, and
+// run-aligned tiling of a level's candidates for both passes of Algorithm 4.
 //
 // Input: the level's keys in generation order (per candidate t0 lo0 hi0 t1
 // ... t_{m-1}) and, for the exact pass, the relaxed counts: the survivors are
@@ -351,6 +351,61 @@ void launch_tile_lanes(int64_t M, const int *scratch, const int *info, int *orig
     const unsigned gM = (unsigned)((M + TB - 1) / TB);
     if (gM) hipLaunchKernelGGL(k_tl_lanes, dim3(gM), dim3(TB), 0, s, part, seg, flag, rx, rs, R,
                                toff, moff, info, orig);
+}
+
+// ---------------------------------------------------------------- join
+// Level m+1 candidates from the frequent m-node episodes F (sorted keys, w
+// ints each): alpha's candidates are alpha's first node and hop followed by
+// each beta in F whose first m-1 nodes and hops equal alpha's last m-1
+// (first[a]: the first such beta; off[a]..off[a+1]: alpha's output range).
+namespace {
+__global__ void k_join(const int *__restrict__ F, int w, const int64_t *__restrict__ first,
+                       const int64_t *__restrict__ off, int64_t cnt, int64_t M,
+                       int *__restrict__ out)
+{
+    const int64_t j = blockIdx.x * (int64_t)TB + threadIdx.x;
+    if (j >= M) return;
+    int64_t lo = 0, hi = cnt;  // last a with off[a] <= j
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= j) lo = mid;
+        else hi = mid;
+    }
+    const int64_t a = lo, b = first[a] + (j - off[a]);
+    const int wo = w + 3;
+    int *o = out + j * wo;
+    const int *al = F + a * w, *be = F + b * w;
+    o[0] = al[0];
+    o[1] = al[1];
+    o[2] = al[2];
+    for (int k = 0; k < w; ++k) o[3 + k] = be[k];
+}
+
+__global__ void k_gather_keys(const int *__restrict__ key, int w, const int *__restrict__ sel,
+                              int nsel, int *__restrict__ out)
+{
+    const int64_t t = blockIdx.x * (int64_t)TB + threadIdx.x;
+    if (t >= (int64_t)nsel * w) return;
+    const int64_t i = t / w;
+    const int k = (int)(t - i * w);
+    out[t] = key[(int64_t)sel[i] * w + k];
+}
+}  // namespace
+
+void launch_join(const int *F, int w, const int64_t *first, const int64_t *off, int64_t cnt,
+                 int64_t M, int *out, hipStream_t s)
+{
+    if (M <= 0 || cnt <= 0) return;
+    hipLaunchKernelGGL(k_join, dim3((unsigned)((M + TB - 1) / TB)), dim3(TB), 0, s, F, w, first,
+                       off, cnt, M, out);
+}
+
+void launch_gather_keys(const int *key, int w, const int *sel, int nsel, int *out, hipStream_t s)
+{
+    const int64_t n = (int64_t)nsel * w;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather_keys, dim3((unsigned)((n + TB - 1) / TB)), dim3(TB), 0, s, key, w,
+                       sel, nsel, out);
 }
 
 }  // namespace fe
