@@ -607,9 +607,21 @@ template <int N, bool EXACT, int D> struct MainRun {
             tm[lane] = 0;
             evs[lane] = make_int2(id, tk);
             if (lane < ce - i) atomicOr(&tm[id & 63], 1ull << lane);
-            unsigned long long ml = 0;
+            // A node-k event (k >= 1) changes the machine only if list k-1
+            // passes at its tick.  When list k-1 passes no tick from the
+            // block's first on, that takes a node k-1 event earlier in the
+            // block that acts, so node k's events up to the first such one
+            // are skipped (the last node's too: it only completes).
+            const int tk0 = __builtin_amdgcn_readfirstlane(tk);
+            unsigned long long eff = tm[c.ty[0] & 63];
+            unsigned long long ml = eff;
 #pragma unroll
-            for (int q = 0; q < N; ++q) ml |= tm[c.ty[q] & 63];
+            for (int q = 1; q < N; ++q) {
+                const unsigned long long mq = tm[c.ty[q] & 63];
+                // (eff ^ (eff - 1): positions up to eff's first; all if none)
+                eff = m.end_of(q - 1) >= tk0 ? mq : (mq & ~(eff ^ (eff - 1ull)));
+                ml |= eff;
+            }
             if (!take) ml = 0;
             while (ml) {
                 const int pos = (int)__builtin_ctzll(ml);
