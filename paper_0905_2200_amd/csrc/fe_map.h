@@ -428,8 +428,6 @@ template <int N, bool EXACT, int D> struct MainRun {
         const int lane = __lane_id();
         const int dty = c.ty[N - 1];
         const int dh = dty & 63;
-        const int bh = u.ty[N - 2] & 63;
-        const int ah = u.ty[N >= 3 ? N - 3 : 0] & 63;
         const int lane4 = lane * 4;
         // wave-uniform bounds: hm[k] the largest hi of hop k, lm[k] >= every
         // lane's end_of(k) (raised at each node k event that may push)
@@ -465,30 +463,29 @@ template <int N, bool EXACT, int D> struct MainRun {
             // positions holding events of this block (a wave-uniform mask)
             const unsigned long long vm = FULL ? ~0ull : (1ull << left) - 1ull;
             const int h = id & 63;
-            const unsigned long long pm =
-                __builtin_amdgcn_ballot_w64(((u.mask >> h) & 1ull) != 0) & vm;
-            const unsigned long long bm = __builtin_amdgcn_ballot_w64(h == bh) & vm;
             tm[lane] = 0;
             evs[lane] = make_int2(id, tk);
             if (v) atomicOr(&tm[h], 1ull << lane);
             unsigned long long ml = tm[dh];
-            unsigned long long remp = pm, remb = bm;
             const int tk0 = __builtin_amdgcn_readfirstlane(tk);
-            if constexpr (N >= 3) {
-                // A node N-2 event changes list N-2 only in a lane whose list
-                // N-3 passes at its tick.  When no lane's list N-3 reaches the
-                // block's first tick, that needs a node N-3 push earlier in
-                // the block, so the events before the first node N-3 event
-                // close no span.
-                const bool none = EXACT ? lm[N - 3] < tk0
-                                        : __builtin_amdgcn_ballot_w64(m.end_of(N - 3) >= tk0) == 0;
-                if (none) {
-                    const unsigned long long am = __builtin_amdgcn_ballot_w64(h == ah) & vm;
-                    // (am ^ (am - 1): positions up to the first such event;
-                    // all of them when there is none)
-                    remb = bm & ~(am ^ (am - 1ull));
-                }
+            // Prefix events that can act, per node: a node-k event (k >= 1)
+            // changes a machine only where list k-1 passes at its tick.  When
+            // no lane's list k-1 passes a tick from the block's first on,
+            // that takes a node k-1 event earlier in the block that acts, so
+            // node k's events up to the first such one are dropped.  Node
+            // N-2's events that can act close the spans.
+            unsigned long long eff = __builtin_amdgcn_ballot_w64(h == (u.ty[0] & 63)) & vm;
+            unsigned long long pm = eff;
+#pragma unroll
+            for (int k = 1; k < N - 1; ++k) {
+                const unsigned long long pk = __builtin_amdgcn_ballot_w64(h == (u.ty[k] & 63)) & vm;
+                const bool live = EXACT ? lm[k - 1] >= tk0
+                                        : __builtin_amdgcn_ballot_w64(m.end_of(k - 1) >= tk0) != 0;
+                // (eff ^ (eff - 1): positions up to eff's first; all if none)
+                eff = live ? pk : (pk & ~(eff ^ (eff - 1ull)));
+                pm |= eff;
             }
+            unsigned long long remp = pm, remb = eff;
             for (;;) {
                 // span: positions up to the lowest closing event (all if none)
                 const unsigned long long rb1 = remb - 1ull;
