@@ -99,7 +99,7 @@ struct fe_ctx {
     fe_stats stats{};
     // workspace
     Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
-    Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn, mkey, tscr, tinfo, mfk, mfo, mfsel;
+    Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn, mkey, tscr, tinfo, mfk, mfo, mfsel, pbc;
     // host arrays of the mining driver, kept for reuse (large ones are pinned)
     ivec keypool, lanepool, uphpool, orderpool;
     int *host = nullptr;  // pinned host staging for small readbacks
@@ -422,14 +422,18 @@ int run_pass(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, 
     int rc;
     if ((rc = ensure(c, c->keys, (size_t)M * sizeof(int)))) return rc;
     if ((rc = ensure(c, c->hist, 2 * NKEYS * sizeof(int)))) return rc;
-    if ((rc = ensure(c, c->fill, NKEYS * sizeof(int)))) return rc;
+    // per-block key counts and their scan (stable placement in key groups)
+    const int64_t nbc = (int64_t)NKEYS * ((M + 255) / 256);
+    if ((rc = ensure(c, c->pbc, (size_t)(2 * nbc + scan_scratch_ints(nbc)) * sizeof(int))))
+        return rc;
+    int *bcnt = P<int>(c->pbc), *boff = bcnt + nbc;
     int *hist = P<int>(c->hist);
     launch_fill(hist, 0, 2 * NKEYS, s);
-    launch_fill(P<int>(c->fill), 0, NKEYS, s);
     {
         KTimer kt(c, "prep_count", 0);
         launch_prep_count(cin.types, cin.len, cin.lo, cin.hi, cin.nmax, sel, nsel, M, num_types,
-                          exact ? 1 : 0, P<int>(c->keys), hist, P<int>(c->status), s);
+                          exact ? 1 : 0, P<int>(c->keys), hist, P<int>(c->status), bcnt, s);
+        launch_scan_excl(bcnt, nbc, boff, boff + nbc, s);
     }
     if ((rc = ensure_host(c, 2 * NKEYS + 1))) return rc;
     HIPCHK(c, hipMemcpyAsync(c->host, hist, NKEYS * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -471,7 +475,7 @@ int run_pass(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, 
         launch_fill(P<int>(c->orig), -1, (int64_t)tiles_total * WAVE, s);
         launch_fill(P<int>(c->tileW), 0, tiles_total, s);
         launch_prep_scatter(cin.types, cin.len, cin.lo, cin.hi, cin.nmax, sel, nsel, M,
-                            P<int>(c->keys), lay, P<int>(c->fill), P<int>(c->pk),
+                            P<int>(c->keys), lay, boff, P<int>(c->pk),
                             P<int>(c->orig), P<int>(c->tileW), s);
     }
 
@@ -626,7 +630,7 @@ extern "C" int fe_destroy(fe_ctx *c)
     Buf *bufs[] = {&c->keys, &c->hist, &c->wmax, &c->fill, &c->pk,    &c->orig,  &c->tileW,
                    &c->lam,  &c->tbl,  &c->flags, &c->sel, &c->nsel,  &c->status, &c->small, &c->cmask,
                    &c->mtypes, &c->mlen, &c->mlo, &c->mhi, &c->mup, &c->mex, &c->msel, &c->mn,
-                   &c->mkey, &c->tscr, &c->tinfo, &c->mfk, &c->mfo, &c->mfsel};
+                   &c->mkey, &c->tscr, &c->tinfo, &c->mfk, &c->mfo, &c->mfsel, &c->pbc};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &p : c->pending) {

@@ -90,11 +90,13 @@ void launch_validate(const int *ids, const int *ticks, int n, int num_types,
 void launch_prep_count(const int *types, const int *len, const int *lo,
                        const int *hi, int nmax, const int *sel,
                        const int *nsel, int M, int num_types, int exact,
-                       int *keys, int *hist, int *status, hipStream_t s);
+                       int *keys, int *hist, int *status, int *bcnt, hipStream_t s);
+// (bcnt: [NKEYS][(M + 255) / 256] per-block counts; boff: their exclusive
+// scan, key-major)
 void launch_prep_scatter(const int *types, const int *len, const int *lo,
                          const int *hi, int nmax, const int *sel,
                          const int *nsel, int M, const int *keys,
-                         const Layout &lay, int *fill, int *pk, int *orig,
+                         const Layout &lay, const int *boff, int *pk, int *orig,
                          int *tileW, hipStream_t s);
 void launch_plan(const int *ticks, int n, const int *tileW, int tiles, int P,
                  int *lam, hipStream_t s);
@@ -118,6 +120,10 @@ void launch_tile_lanes(int64_t M, const int *scratch, const int *info, int *orig
 void launch_join(const int *F, int w, const int64_t *first, const int64_t *off, int64_t cnt,
                  int64_t M, int *out, hipStream_t s);
 void launch_gather_keys(const int *key, int w, const int *sel, int nsel, int *out, hipStream_t s);
+// Exclusive scan of n ints (scratch: scan_scratch_ints(n) ints; its first
+// holds the total).
+int64_t scan_scratch_ints(int64_t n);
+void launch_scan_excl(const int *in, int64_t n, int *out, int *scratch, hipStream_t s);
 void launch_persist_fixup(int N, bool exact, int dcls, const BatchDev &b, const int *ctiles,
                           int nct, hipStream_t s);
 void launch_plan_batch(const TileDesc *tiles, const BJob *jobs, const int *tileW,

@@ -107,11 +107,15 @@ __device__ int wave_reserve(int key, int *counter)
     return pos;
 }
 
-// hist[key] += candidates with that key; hist[NKEYS + key] = max W among them.
+// hist[key] += candidates with that key; hist[NKEYS + key] = max W among them;
+// bcnt[key * nb + block] = the block's candidates with that key.
 __global__ void k_prep_count(const int *types, const int *len, const int *lo, const int *hi,
                              int nmax, const int *sel, const int *nsel, int M, int num_types,
-                             int exact, int *keys, int *hist, int *status)
+                             int exact, int *keys, int *hist, int *status, int *bcnt, int nb)
 {
+    __shared__ int sc[NKEYS];
+    if (threadIdx.x < NKEYS) sc[threadIdx.x] = 0;
+    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = __lane_id();
     const int lim = nsel ? *nsel : M;
@@ -139,55 +143,84 @@ __global__ void k_prep_count(const int *types, const int *len, const int *lo, co
         if (lane == leader) {
             atomicAdd(&hist[k0], cntk);
             atomicMax(&hist[NKEYS + k0], wm);
+            atomicAdd(&sc[k0], cntk);
         }
         pending = pending && !mine;
     }
+    __syncthreads();
+    if (threadIdx.x < NKEYS) bcnt[(int64_t)threadIdx.x * nb + blockIdx.x] = sc[threadIdx.x];
 }
 
 void launch_prep_count(const int *types, const int *len, const int *lo, const int *hi, int nmax,
                        const int *sel, const int *nsel, int M, int num_types, int exact,
-                       int *keys, int *hist, int *status, hipStream_t s)
+                       int *keys, int *hist, int *status, int *bcnt, hipStream_t s)
 {
     if (M <= 0) return;
-    hipLaunchKernelGGL(k_prep_count, dim3((M + 255) / 256), dim3(256), 0, s, types, len, lo, hi,
-                       nmax, sel, nsel, M, num_types, exact, keys, hist, status);
+    const int nb = (M + 255) / 256;
+    hipLaunchKernelGGL(k_prep_count, dim3(nb), dim3(256), 0, s, types, len, lo, hi, nmax, sel,
+                       nsel, M, num_types, exact, keys, hist, status, bcnt, nb);
 }
 
+// Each candidate goes to its key group in input order: its rank is the
+// group's candidates in earlier blocks (boff: exclusive scan of the per-block
+// counts, key-major), then in earlier waves of the block, then in earlier
+// lanes -- so runs of siblings given in order stay together.
 __global__ void k_prep_scatter(const int *types, const int *len, const int *lo, const int *hi,
                                int nmax, const int *sel, const int *nsel, int M,
-                               const int *keys, Layout lay, int *fill, int *pk, int *orig,
-                               int *tileW)
+                               const int *keys, Layout lay, const int *boff, int nb, int *pk,
+                               int *orig, int *tileW)
 {
+    constexpr int WV = 256 / WAVE;
+    __shared__ int wc[WV][NKEYS];
+    if (threadIdx.x < WV * NKEYS) (&wc[0][0])[threadIdx.x] = 0;
+    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = __lane_id(), wv = threadIdx.x >> 6;
     const int lim = nsel ? *nsel : M;
     const int key = i < lim ? keys[i] : -1;
-    const int r = wave_reserve(key, fill);
+    int rank = 0;
+    bool pending = key >= 0;
+    for (;;) {
+        const unsigned long long act = __ballot(pending);
+        if (act == 0) break;
+        const int leader = __ffsll((long long)act) - 1;
+        const int k0 = __shfl(key, leader);
+        const bool mine = pending && key == k0;
+        const unsigned long long mask = __ballot(mine);
+        if (mine) rank = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == leader) wc[wv][k0] = __popcll(mask);
+        pending = pending && !mine;
+    }
+    __syncthreads();
     if (key < 0) return;
+    for (int w = 0; w < wv; ++w) rank += wc[w][key];
+    const int r = boff[(int64_t)key * nb + blockIdx.x] - boff[(int64_t)key * nb] + rank;
     const int m = sel ? sel[i] : i;
     const int N = key / NDCLS + 1;
     const int tile = lay.tile_base[key] + r / WAVE;
-    const int lane = r % WAVE;
+    const int tl = r % WAVE;  // lane of the tile
     int *rec = pk + lay.rec_base[key] + (int64_t)(r / WAVE) * rec_ints(N);
     const int64_t tb = (int64_t)m * nmax, ib = (int64_t)m * (nmax - 1);
     int W = 0;
-    for (int k = 0; k < N; ++k) rec[k * WAVE + lane] = types[tb + k];
+    for (int k = 0; k < N; ++k) rec[k * WAVE + tl] = types[tb + k];
     for (int k = 0; k < N - 1; ++k) {
-        rec[(N + k) * WAVE + lane] = lo[ib + k];
-        rec[(2 * N - 1 + k) * WAVE + lane] = hi[ib + k];
+        rec[(N + k) * WAVE + tl] = lo[ib + k];
+        rec[(2 * N - 1 + k) * WAVE + tl] = hi[ib + k];
         W += hi[ib + k];
     }
-    orig[(int64_t)tile * WAVE + lane] = m;
+    orig[(int64_t)tile * WAVE + tl] = m;
     atomicMax(&tileW[tile], W);
 }
 
 void launch_prep_scatter(const int *types, const int *len, const int *lo, const int *hi,
                          int nmax, const int *sel, const int *nsel, int M, const int *keys,
-                         const Layout &lay, int *fill, int *pk, int *orig, int *tileW,
+                         const Layout &lay, const int *boff, int *pk, int *orig, int *tileW,
                          hipStream_t s)
 {
     if (M <= 0) return;
-    hipLaunchKernelGGL(k_prep_scatter, dim3((M + 255) / 256), dim3(256), 0, s, types, len, lo,
-                       hi, nmax, sel, nsel, M, keys, lay, fill, pk, orig, tileW);
+    const int nb = (M + 255) / 256;
+    hipLaunchKernelGGL(k_prep_scatter, dim3(nb), dim3(256), 0, s, types, len, lo, hi, nmax, sel,
+                       nsel, M, keys, lay, boff, nb, pk, orig, tileW);
 }
 
 // ------------------------------------------------------------------ segment plan

@@ -392,6 +392,13 @@ __global__ void k_gather_keys(const int *__restrict__ key, int w, const int *__r
 }
 }  // namespace
 
+int64_t scan_scratch_ints(int64_t n) { return (n + CHUNK - 1) / CHUNK + 1; }
+
+void launch_scan_excl(const int *in, int64_t n, int *out, int *scratch, hipStream_t s)
+{
+    scan(Arr{in}, nullptr, n, out, scratch + 1, scratch, s);
+}
+
 void launch_join(const int *F, int w, const int64_t *first, const int64_t *off, int64_t cnt,
                  int64_t M, int *out, hipStream_t s)
 {
