@@ -189,13 +189,20 @@ template <int N, int D> struct Exact {
 #pragma unroll
         for (int k = 0; k < N - 1; ++k)
 #pragma unroll
-            for (int d = 0; d < D; ++d) wb[k][d] = GONE;
+            for (int d = 0; d < D; ++d) {
+                wa[k][d] = EMPTY;
+                wb[k][d] = GONE;
+            }
     }
+    // t in [wa, wb] as one unsigned compare per window: t - wa <= wb - wa
+    // (mod 2^32).  Live windows have wa <= wb and ticks below 2^30; an unused
+    // slot (EMPTY, GONE) gives wb - wa = 1 and t - wa >= 2^31.
     __device__ __forceinline__ bool hit(int k, int t) const
     {
         bool h = false;
 #pragma unroll
-        for (int d = 0; d < D; ++d) h |= (wa[k][d] <= t) & (t <= wb[k][d]);
+        for (int d = 0; d < D; ++d)
+            h |= (unsigned)t - (unsigned)wa[k][d] <= (unsigned)wb[k][d] - (unsigned)wa[k][d];
         return h;
     }
     // Latest tick a window of list k covers (GONE when the list is empty):
