@@ -97,8 +97,8 @@ typedef enum fe_param {
     FE_PARAM_CROSSOVER_A = 6, /* hybrid rule (Algorithm 2, Eq. 2): a group of  */
     FE_PARAM_CROSSOVER_B = 7, /* tiles >= A/N + B tiles of N-node candidates is
                                 counted whole-stream (P = 1), a smaller one by
-                                MapConcatenate with P >= 2.  Defaults 24200 and
-                                6926: fitted to crossovers measured on a 256-CU
+                                MapConcatenate with P >= 2.  Defaults 548 and
+                                12651: fitted to crossovers measured on a 256-CU
                                 MI355X (python -m paper_0905_2200_amd.crossover).
                                 Ignored when FE_PARAM_SEGMENTS > 0.           */
     FE_PARAM_ELIMINATION = 8, /* fe_mine: 1 (default) = two-pass elimination

@@ -95,7 +95,7 @@ struct fe_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
-    int64_t param[10] = {0, 4096, 1024, 1, 0, 1, 24200, 6926, 1, 0};
+    int64_t param[10] = {0, 4096, 1024, 1, 0, 1, 548, 12651, 1, 0};
     fe_stats stats{};
     // workspace
     Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
