@@ -98,7 +98,7 @@ struct fe_ctx {
     int64_t param[10] = {0, 4096, 1024, 1, 0, 1, 548, 12651, 1, 0};
     fe_stats stats{};
     // workspace
-    Buf keys, hist, wmax, fill, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
+    Buf keys, hist, wmax, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
     Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn, mkey, tscr, tinfo, mfk, mfo, mfsel, pbc;
     // host arrays of the mining driver, kept for reuse (large ones are pinned)
     ivec keypool, lanepool, uphpool, orderpool;
@@ -627,7 +627,7 @@ extern "C" int fe_destroy(fe_ctx *c)
     if (!c) return FE_EINVAL;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    Buf *bufs[] = {&c->keys, &c->hist, &c->wmax, &c->fill, &c->pk,    &c->orig,  &c->tileW,
+    Buf *bufs[] = {&c->keys, &c->hist, &c->wmax, &c->pk,    &c->orig,  &c->tileW,
                    &c->lam,  &c->tbl,  &c->flags, &c->sel, &c->nsel,  &c->status, &c->small, &c->cmask,
                    &c->mtypes, &c->mlen, &c->mlo, &c->mhi, &c->mup, &c->mex, &c->msel, &c->mn,
                    &c->mkey, &c->tscr, &c->tinfo, &c->mfk, &c->mfo, &c->mfsel, &c->pbc};
