@@ -135,6 +135,8 @@ def main():
                          "window requests from 32 arrays, open-loop Poisson trace")
     ap.add_argument("--trace-s", type=float, default=20.0, help="served: trace length (s)")
     ap.add_argument("--rate", type=float, default=200.0, help="served: requests per second")
+    ap.add_argument("--max-inflight", type=int, default=3,
+                    help="served: rounds on the device at once (one stream each)")
     ap.add_argument("--partition-s", type=float, default=10.0,
                     help="streaming: seconds of recording per partition")
     ap.add_argument("--one-pass", action="store_true",
@@ -473,7 +475,7 @@ def bench_served(args):
     # ---------------------------------------------------------------- served
     server = fe.Server(ctx, sv["candidates"], [a["num_types"] for a in arrays],
                        capacity=max(a["ids"].size for a in arrays) + 16,
-                       hbm_budget=16 << 30, max_inflight=3, max_round=64)
+                       hbm_budget=16 << 30, max_inflight=args.max_inflight, max_round=64)
     ptr = [0] * len(arrays)
 
     def feed(upto):  # append every array's events with tick < upto
