@@ -46,10 +46,14 @@
  *   lo[M * (nmax-1)]      lo_k of hop k in lo[m*(nmax-1) + k], k < N-1;
  *   hi[M * (nmax-1)]      hi_k likewise.  0 <= lo_k < hi_k < 2^30 and
  *                         sum_k hi_k < 2^30.
- *   For FE_EXACT, each hop must also satisfy hi/(hi-lo+1) < 8 (integer
- *   division), which bounds the live state of Algorithm 1's lists; every
- *   interval with lo <= 0.75*hi meets it (e.g. (0,5], (5,10], (10,15],
- *   (10,20] ms).  A hop outside it is rejected with FE_EINVAL.
+ *   Every such hop is counted exactly.  Algorithm 1's list for hop k matters
+ *   only through the ticks that pass its test, a union of windows of which
+ *   at most hi_k/(hi_k-lo_k+1)+1 are live at once.  Candidates whose hops
+ *   all have at most 8 live windows keep their lists in registers; the
+ *   others (narrow intervals far from 0, e.g. (190,200] ticks) keep them as
+ *   rings in library-owned device memory, min(bound, n) windows per list,
+ *   and are counted over the whole stream by a kernel of their own.  If one
+ *   candidate's rings cannot be allocated the call returns FE_ENOMEM.
  */
 #ifndef FE_H
 #define FE_H

@@ -100,6 +100,7 @@ struct fe_ctx {
     // workspace
     Buf keys, hist, wmax, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
     Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn, mkey, tscr, tinfo, mfk, mfo, mfsel, pbc;
+    Buf deep;  // window rings of the deep-class exact launches
     // host arrays of the mining driver, kept for reuse (large ones are pinned)
     ivec keypool, lanepool, uphpool, orderpool;
     int *host = nullptr;  // pinned host staging for small readbacks
@@ -261,7 +262,7 @@ const char *status_text(int bits)
 {
     if (bits & ST_BADCAND)
         return "invalid candidate (N outside [1,nmax], type outside [0,num_types), "
-               "lo<0, lo>=hi, hi or sum(hi) >= 2^30, or hi/(hi-lo+1) >= 8 for FE_EXACT)";
+               "lo<0, lo>=hi, or hi or sum(hi) >= 2^30)";
     if (bits & ST_RANGE) return "event id outside [0,num_types) or tick outside [0,2^30)";
     if (bits & ST_UNSORTED) return "event ticks are not non-decreasing";
     if (bits & ST_INTERNAL) return "internal invariant failed";
@@ -307,7 +308,8 @@ int choose_P(const fe_ctx *c, int tiles, const StreamInfo &si, int Wmax, int N)
 
 // One candidate group (episode size and list-depth class) already packed
 // in the tile table: tiles [tile_base, tile_base+tiles), records from int
-// offset rec_base, widest W (sum of hi) wmax, real candidates ncand.
+// offset rec_base, widest W (sum of hi) wmax, real candidates ncand, and
+// for the deep class the largest window bound of its hops (dcap).
 struct GroupDesc {
     int key;
     int tiles;
@@ -315,7 +317,42 @@ struct GroupDesc {
     int64_t rec_base;
     int wmax;
     int64_t ncand;
+    int dcap = 0;
 };
+
+// Launch plan of a deep-class group over a stream of n events: each lane's
+// N-1 lists hold cap = min(dcap, n) windows (live windows of a list number at
+// most its hop's window bound, and at most the events of the range
+// [t - hi, t]); lanes are processed in chunks whose rings fit the scratch
+// budget (at least one lane per chunk).
+struct DeepPlan {
+    int cap = 1;
+    int64_t chunk = 0;   // lanes per launch
+    int64_t bytes = 0;   // ring bytes of one launch
+};
+
+DeepPlan deep_plan(int N, int64_t lanes, int dcap, int n, int64_t budget = DEEP_SCRATCH)
+{
+    DeepPlan p;
+    p.cap = std::max(1, std::min(dcap, std::max(n, 1)));
+    const int64_t per = (int64_t)std::max(N - 1, 1) * p.cap * (int64_t)sizeof(int2);
+    p.chunk = std::max<int64_t>(1, std::min<int64_t>(lanes, budget / per));
+    if (p.chunk >= WAVE) p.chunk = p.chunk / WAVE * WAVE;
+    p.bytes = p.chunk * per;
+    return p;
+}
+
+// Enqueue the chunks of a deep-class group (a: everything but the lane range
+// and the ring capacity); `lanes` = the group's tiles * 64.
+void deep_launch(int N, DeepArgs a, const DeepPlan &p, int64_t lanes, hipStream_t s)
+{
+    a.cap = p.cap;
+    for (int64_t g0 = 0; g0 < lanes; g0 += p.chunk) {
+        a.g0 = g0;
+        a.g1 = std::min(lanes, g0 + p.chunk);
+        launch_deep(N, a, s);
+    }
+}
 
 // Incremental count (fe_count_resume): events before `from` were counted by
 // earlier calls; per candidate, count_io / last_io carry the count and the
@@ -344,6 +381,33 @@ int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo 
         const int k = gd.key;
         const int N = k / NDCLS + 1, dcls = k % NDCLS;
         const int tiles = gd.tiles;
+        if (exact && dcls == DEEP_CLS) {
+            // lists beyond 8 windows: rings in device memory, whole stream
+            const int64_t lanes = (int64_t)tiles * WAVE;
+            const DeepPlan dp = deep_plan(N, lanes, gd.dcap, si.n);
+            if ((rc = ensure(c, c->deep, (size_t)dp.bytes))) return rc;
+            DeepArgs a{};
+            a.ids = ids;
+            a.ticks = ticks;
+            a.n = si.n;
+            a.pk = P<int>(c->pk) + gd.rec_base;
+            a.orig = P<int>(c->orig) + (int64_t)gd.tile_base * WAVE;
+            a.ring = P<int2>(c->deep);
+            a.out = out;
+            a.status = P<int>(c->status);
+            if (rs) {
+                a.from = rs->from;
+                a.count_io = rs->count_io;
+                a.last_io = rs->last_io;
+            }
+            c->stats.map_launches++;
+            char dname[40];
+            snprintf(dname, sizeof dname, "%s_exact_n%d_deep", rs ? "resume" : "map", N);
+            KTimer kt(c, dname, (double)gd.ncand * (double)(si.n - (rs ? rs->from : 0)));
+            deep_launch(N, a, dp, lanes, s);
+            HIPCHK(c, hipGetLastError());
+            continue;
+        }
         MapGroup g;
         g.ids = ids;
         g.ticks = ticks;
@@ -421,36 +485,35 @@ int run_pass(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, 
     hipStream_t s = c->stream;
     int rc;
     if ((rc = ensure(c, c->keys, (size_t)M * sizeof(int)))) return rc;
-    if ((rc = ensure(c, c->hist, 2 * NKEYS * sizeof(int)))) return rc;
+    if ((rc = ensure(c, c->hist, 3 * NKEYS * sizeof(int)))) return rc;
     // per-block key counts and their scan (stable placement in key groups)
     const int64_t nbc = (int64_t)NKEYS * ((M + 255) / 256);
     if ((rc = ensure(c, c->pbc, (size_t)(2 * nbc + scan_scratch_ints(nbc)) * sizeof(int))))
         return rc;
     int *bcnt = P<int>(c->pbc), *boff = bcnt + nbc;
     int *hist = P<int>(c->hist);
-    launch_fill(hist, 0, 2 * NKEYS, s);
+    launch_fill(hist, 0, 3 * NKEYS, s);
     {
         KTimer kt(c, "prep_count", 0);
         launch_prep_count(cin.types, cin.len, cin.lo, cin.hi, cin.nmax, sel, nsel, M, num_types,
                           exact ? 1 : 0, P<int>(c->keys), hist, P<int>(c->status), bcnt, s);
         launch_scan_excl(bcnt, nbc, boff, boff + nbc, s);
     }
-    if ((rc = ensure_host(c, 2 * NKEYS + 1))) return rc;
-    HIPCHK(c, hipMemcpyAsync(c->host, hist, NKEYS * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->host + NKEYS + 1, hist + NKEYS, NKEYS * sizeof(int),
-                             hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(c->host + NKEYS, P<int>(c->status), sizeof(int),
+    if ((rc = ensure_host(c, 3 * NKEYS + 1))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->host, hist, 3 * NKEYS * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->host + 3 * NKEYS, P<int>(c->status), sizeof(int),
                              hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     HIPCHK(c, hipGetLastError());
-    const int bits = c->host[NKEYS];
+    const int bits = c->host[3 * NKEYS];
     if (bits) {
         launch_fill(P<int>(c->status), 0, 1, s);
         return fail(c, status_code(bits), "%s", status_text(bits));
     }
-    int cnt[NKEYS], wmax[NKEYS];
+    int cnt[NKEYS], wmax[NKEYS], bmax[NKEYS];
     std::memcpy(cnt, c->host, sizeof cnt);
-    std::memcpy(wmax, c->host + NKEYS + 1, sizeof wmax);
+    std::memcpy(wmax, c->host + NKEYS, sizeof wmax);
+    std::memcpy(bmax, c->host + 2 * NKEYS, sizeof bmax);
 
     Layout lay;
     int tiles_total = 0;
@@ -483,7 +546,8 @@ int run_pass(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, 
     for (int k = 0; k < NKEYS; ++k)
         if (cnt[k])
             groups.push_back(GroupDesc{k, (cnt[k] + WAVE - 1) / WAVE, lay.tile_base[k],
-                                       (int64_t)lay.rec_base[k], wmax[k], (int64_t)cnt[k]});
+                                       (int64_t)lay.rec_base[k], wmax[k], (int64_t)cnt[k],
+                                       bmax[k]});
     return launch_groups(c, ids, ticks, si, groups, exact, out, rs);
 }
 
@@ -613,7 +677,7 @@ extern "C" int fe_create(int device, void *hip_stream, fe_ctx **out)
     c->device = device;
     c->stream = (hipStream_t)hip_stream;  // NULL: the device's null stream
     c->own_stream = false;
-    if (ensure(c, c->status, sizeof(int)) || ensure_host(c, 64)) {
+    if (ensure(c, c->status, sizeof(int)) || ensure_host(c, 256)) {
         fe_destroy(c);
         return FE_ENOMEM;
     }
@@ -630,7 +694,8 @@ extern "C" int fe_destroy(fe_ctx *c)
     Buf *bufs[] = {&c->keys, &c->hist, &c->wmax, &c->pk,    &c->orig,  &c->tileW,
                    &c->lam,  &c->tbl,  &c->flags, &c->sel, &c->nsel,  &c->status, &c->small, &c->cmask,
                    &c->mtypes, &c->mlen, &c->mlo, &c->mhi, &c->mup, &c->mex, &c->msel, &c->mn,
-                   &c->mkey, &c->tscr, &c->tinfo, &c->mfk, &c->mfo, &c->mfsel, &c->pbc};
+                   &c->mkey, &c->tscr, &c->tinfo, &c->mfk, &c->mfo, &c->mfsel, &c->pbc,
+                   &c->deep};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &p : c->pending) {
@@ -1002,15 +1067,17 @@ struct HostPack {
     int tiles = 0;
 };
 
+// largest window bound of an episode key's hops
+int host_bound(const int *k, int m)
+{
+    int bound = 1;
+    for (int j = 0; j < m - 1; ++j) bound = std::max(bound, window_bound(k[3 * j + 1], k[3 * j + 2]));
+    return bound;
+}
+
 int host_dcls(const int *k, int m, bool exact)
 {
-    if (!exact) return 0;
-    int bound = 1;
-    for (int j = 0; j < m - 1; ++j) {
-        const int lo = k[3 * j + 1], hi = k[3 * j + 2];
-        bound = std::max(bound, hi / (hi - lo + 1) + 1);
-    }
-    return bound <= 1 ? 0 : bound <= 2 ? 1 : bound <= 4 ? 2 : 3;
+    return exact ? depth_class(host_bound(k, m)) : 0;
 }
 
 // order: the candidates to pack (indices into C), or null for all of C in
@@ -1125,16 +1192,19 @@ void host_pack(const Episodes &C, const int *order, int64_t n, bool exact, HostP
             }
         });
         std::fill(lanes.begin() + run_tiles * WAVE + nmixed, lanes.end(), -1);
+        int dcap = 0;  // largest window bound of the deep class
+        if (exact && cls == DEEP_CLS)
+            for (int64_t i = 0; i < V; ++i) dcap = std::max(dcap, host_bound(C.at(vat(i)), m));
         if (wmax_bound >= 0) {
             GroupDesc gd{(m - 1) * NDCLS + cls, tiles, hp.tiles, (int64_t)hp.tiles * ri,
-                         wmax_bound, V};
+                         wmax_bound, V, dcap};
             if (hp.orig.empty()) hp.orig.swap(lanes);
             else hp.orig.insert(hp.orig.end(), lanes.begin(), lanes.end());
             hp.tiles += tiles;
             hp.groups.push_back(gd);
             continue;
         }
-        GroupDesc gd{(m - 1) * NDCLS + cls, tiles, hp.tiles, (int64_t)hp.rec.size(), 0, V};
+        GroupDesc gd{(m - 1) * NDCLS + cls, tiles, hp.tiles, (int64_t)hp.rec.size(), 0, V, dcap};
         const size_t rec0 = hp.rec.size(), orig0 = hp.orig.size(), tw0 = hp.tileW.size();
         hp.rec.resize(rec0 + (size_t)tiles * ri);
         hp.orig.resize(orig0 + (size_t)tiles * WAVE);
@@ -1216,7 +1286,7 @@ int upload_pack(fe_ctx *c, const HostPack &hp)
 // widths of the candidates kept (all, or upper >= theta when up is set),
 // grouped by list-depth class when exact.  kept: their number.
 int dev_pack(fe_ctx *c, const int *key_d, int m, int64_t M, const int *up, int theta,
-             bool exact, int wbound, std::vector<GroupDesc> &groups, int64_t &kept)
+             bool exact, int wbound, int bbound, std::vector<GroupDesc> &groups, int64_t &kept)
 {
     int rc;
     hipStream_t s = c->stream;
@@ -1254,7 +1324,7 @@ int dev_pack(fe_ctx *c, const int *key_d, int m, int64_t M, const int *up, int t
         if (info[k] > 0)
             groups.push_back(GroupDesc{(m - 1) * NDCLS + k, info[k], info[NDCLS + k],
                                        (int64_t)info[NDCLS + k] * ri, wbound,
-                                       (int64_t)info[4 * NDCLS + k]});
+                                       (int64_t)info[4 * NDCLS + k], bbound});
     return FE_OK;
 }
 
@@ -1275,7 +1345,7 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
     std::vector<int> ilo(iv_lo, iv_lo + n_iv), ihi(iv_hi, iv_hi + n_iv);
     for (int k = 0; k < n_iv; ++k) {
         const int l = ilo[k], h = ihi[k];
-        if (l < 0 || l >= h || h >= TICK_LIMIT || h / (h - l + 1) >= 8)
+        if (l < 0 || l >= h || h >= TICK_LIMIT)
             return fail(c, FE_EINVAL, "interval %d = (%d,%d] invalid", k, l, h);
         if ((int64_t)h * max_level >= TICK_LIMIT)
             return fail(c, FE_EINVAL, "interval %d too wide for max_level", k);
@@ -1345,6 +1415,8 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         int *up = P<int>(c->mup), *ex = P<int>(c->mex);
         // the level's keys go to the device once; tile records are built there
         const int wbound = (level - 1) * *std::max_element(ihi.begin(), ihi.end());
+        int bbound = 1;  // largest window bound of the interval set
+        for (int k = 0; k < n_iv; ++k) bbound = std::max(bbound, window_bound(ilo[k], ihi[k]));
         const int wk = 3 * level - 2;  // ints per key
         if ((rc = ensure(c, c->mkey, std::max<size_t>(M * wk, 1) * sizeof(int)))) return rc;
         if (djoin) {
@@ -1380,7 +1452,7 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
             std::vector<GroupDesc> groups;
             if (elim) {
                 if ((rc = dev_pack(c, P<int>(c->mkey), level, (int64_t)M, nullptr, 0, false,
-                                   wbound, groups, kept)))
+                                   wbound, bbound, groups, kept)))
                     return rc;
                 if ((rc = launch_groups(c, ids, ticks, si, groups, false, up))) return rc;
             } else {
@@ -1388,7 +1460,7 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
             }
             launch_fill(ex, -1, (int64_t)M, s);
             if ((rc = dev_pack(c, P<int>(c->mkey), level, (int64_t)M, elim ? up : nullptr, theta,
-                               true, wbound, groups, kept)))
+                               true, wbound, bbound, groups, kept)))
                 return rc;
             if (kept > 0 && (rc = launch_groups(c, ids, ticks, si, groups, true, ex))) return rc;
         } else if (elim) {
@@ -1556,14 +1628,14 @@ struct fe_batch {
     std::vector<StreamInfo> si;
     // tiling (independent of the launch shape)
     struct Group {
-        int job, key, t0, tiles, wmax;
+        int job, key, t0, tiles, wmax, dcap;
     };
     std::vector<Group> groups;
     std::vector<int> rec, orig, tileW;
     int ntiles = 0;
     fe_batch_tuning tun{32768, 16, 0.0};
     // device
-    Buf pk, origd, tileWd, tilesd, jobsd, itemsd, listsd, lamd, tbld, flagsr, flagsx, qctr;
+    Buf pk, origd, tileWd, tilesd, jobsd, itemsd, listsd, lamd, tbld, flagsr, flagsx, qctr, deepd;
     struct Level {
         int N;
         hipGraph_t g = nullptr;
@@ -1670,6 +1742,7 @@ int batch_plan(fe_batch *b)
         };
         add_items(tl, L.it_rel, L.n_rel);
         for (int d = 0; d < NDCLS; ++d) {
+            if (d == DEEP_CLS) continue;  // counted by k_deep, whole stream
             std::vector<int> td_d;
             for (int t : tl)
                 if (tileD[t] == d) td_d.push_back(t);
@@ -1694,8 +1767,23 @@ int batch_plan(fe_batch *b)
         bj[j].upper = b->jobs[j].upper_out;
         bj[j].exact = b->jobs[j].exact_out;
     }
+    // deep-class groups: the exact pass by k_deep over the recording's stream
+    struct DeepJob {
+        int N, job, t0, tiles;
+        DeepPlan dp;
+    };
+    std::vector<DeepJob> dj;
+    int64_t deep_bytes = 0;
+    for (const auto &g : b->groups) {
+        if (g.key % NDCLS != DEEP_CLS) continue;
+        const int N = g.key / NDCLS + 1;
+        const DeepPlan dp = deep_plan(N, (int64_t)g.tiles * WAVE, g.dcap, (int)b->jobs[g.job].n);
+        deep_bytes = std::max(deep_bytes, dp.bytes);
+        dj.push_back(DeepJob{N, g.job, g.t0, g.tiles, dp});
+    }
     hipStream_t s = c->stream;
     HIPCHK(c, hipStreamSynchronize(s));
+    if (deep_bytes > 0 && (rc = ensure(c, b->deepd, (size_t)deep_bytes))) return rc;
     if ((rc = ensure(c, b->tilesd, std::max<size_t>(td.size(), 1) * sizeof(TileDesc)))) return rc;
     if ((rc = ensure(c, b->jobsd, std::max<size_t>(bj.size(), 1) * sizeof(BJob)))) return rc;
     if ((rc = ensure(c, b->itemsd, std::max<size_t>(items.size(), 1) * sizeof(int2)))) return rc;
@@ -1758,10 +1846,27 @@ int batch_plan(fe_batch *b)
             d.qctr = P<int>(b->qctr) + q++;
             launch_persist(L.N, true, dd, d, grid, cs);
         }
-        launch_concat_batch(d, lists_d + L.pl, (int)L.npl, true, cs);
         for (int dd = 0; dd < NDCLS; ++dd)
-            if (L.npld[dd])
+            if (L.npld[dd]) {
+                launch_concat_batch(d, lists_d + L.pld[dd], (int)L.npld[dd], true, cs);
                 launch_persist_fixup(L.N, true, dd, d, lists_d + L.pld[dd], (int)L.npld[dd], cs);
+            }
+        for (const DeepJob &x : dj) {
+            if (x.N != L.N) continue;
+            const fe_job &j = b->jobs[x.job];
+            DeepArgs a{};
+            a.ids = j.ids;
+            a.ticks = j.ticks;
+            a.n = (int)j.n;
+            a.pk = P<int>(b->pk) + td[x.t0].rec;
+            a.orig = P<int>(b->origd) + (int64_t)x.t0 * WAVE;
+            a.ring = P<int2>(b->deepd);
+            a.out = j.exact_out;
+            a.upper = j.upper_out;
+            a.theta = j.theta;
+            a.status = P<int>(c->status);
+            deep_launch(x.N, a, x.dp, (int64_t)x.tiles * WAVE, cs);
+        }
         hipError_t e1 = hipStreamEndCapture(b->cap, &lv.g);
         if (e1 != hipSuccess) return fail(c, FE_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1));
         HIPCHK(c, hipGraphInstantiate(&lv.x, lv.g, nullptr, nullptr, 0));
@@ -1837,7 +1942,7 @@ extern "C" int fe_batch_create(fe_ctx *c, int32_t R, const fe_job *jobs, fe_batc
                     C.key.push_back(t);
                     if (k < N - 1) {
                         const int l = lo[(size_t)m * (nm - 1) + k], h = hi[(size_t)m * (nm - 1) + k];
-                        if (l < 0 || l >= h || h >= TICK_LIMIT || h / (h - l + 1) >= 8)
+                        if (l < 0 || l >= h || h >= TICK_LIMIT)
                             return bail(fail(c, FE_EINVAL, "job %d: bad interval", r));
                         W += h;
                         C.key.push_back(l);
@@ -1851,7 +1956,8 @@ extern "C" int fe_batch_create(fe_ctx *c, int32_t R, const fe_job *jobs, fe_batc
             HostPack hp;
             host_pack(C, nullptr, (int64_t)back.size(), true, hp);
             for (const GroupDesc &gd : hp.groups) {
-                fe_batch::Group g{r, gd.key, b->ntiles + gd.tile_base, gd.tiles, gd.wmax};
+                fe_batch::Group g{r, gd.key, b->ntiles + gd.tile_base, gd.tiles, gd.wmax,
+                                  gd.dcap};
                 b->groups.push_back(g);
             }
             b->rec.insert(b->rec.end(), hp.rec.begin(), hp.rec.end());
@@ -1946,7 +2052,8 @@ extern "C" int fe_batch_destroy(fe_batch *b)
     (void)hipStreamSynchronize(c->stream);
     batch_free_graphs(b);
     Buf *bufs[] = {&b->pk,    &b->origd, &b->tileWd, &b->tilesd, &b->jobsd,  &b->itemsd,
-                   &b->listsd, &b->lamd, &b->tbld,   &b->flagsr, &b->flagsx, &b->qctr};
+                   &b->listsd, &b->lamd, &b->tbld,   &b->flagsr, &b->flagsx, &b->qctr,
+                   &b->deepd};
     for (Buf *x : bufs)
         if (x->p) (void)hipFree(x->p);
     if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -2021,7 +2128,9 @@ struct fe_server {
         bool busy = false;
         std::vector<Req *> reqs;
         Buf arena, outd, descd, jobsd;
-        int *hout = nullptr;     // pinned results
+        Buf statd;               // device status word of the lane's rounds
+        Buf deepd;               // window rings of deep-class candidates
+        int *hout = nullptr;     // pinned results, then the round's status word
         char *hstage = nullptr;  // pinned staging for descriptors and items
         size_t stage_cap = 0;
     };
@@ -2042,8 +2151,6 @@ namespace {
 int64_t req_arena_bytes(const fe_server *sv, int n)
 {
     int64_t tot = 0;
-    const int span_guess = 1;
-    (void)span_guess;
     for (const GroupDesc &g : sv->groups) {
         const int P = std::max(1, (int)std::min<int64_t>(256, (n + sv->cfg.seg_events - 1) /
                                                              std::max(1, sv->cfg.seg_events)));
@@ -2131,6 +2238,7 @@ int server_launch(fe_server *sv, fe_server::Lane &ln)
         };
         add_items(tl, L.it_rel, L.n_rel);
         for (int d = 0; d < NDCLS; ++d) {
+            if (d == DEEP_CLS) continue;  // counted by k_deep, whole stream
             std::vector<int> tdd;
             for (int t : tl)
                 if (descD[t] == d) tdd.push_back(t);
@@ -2201,12 +2309,13 @@ int server_launch(fe_server *sv, fe_server::Lane &ln)
     d.orig = P<int>(sv->origd);
     d.lam = (int *)(ar + o_lam);
     d.tbl = (int2 *)(ar + o_tbl);
-    d.status = P<int>(c->status);
+    d.status = P<int>(ln.statd);
     d.sparse = c->param[FE_PARAM_TYPE_DISPATCH] != 0;
     int *lists_d = (int *)(ar + o_lists);
     int *fr = (int *)(ar + o_fr), *fx = (int *)(ar + o_fx), *qc = (int *)(ar + o_q);
     const int grid = std::max(1, sv->ncu * sv->cfg.waves_per_cu / WPB);
     launch_fill(qc, 0, NMAX * (1 + NDCLS), s);
+    launch_fill(P<int>(ln.statd), 0, 1, s);
     int q = 0;
     for (const LvPlan &L : lp) {
         launch_clear_flags(lists_d + L.pl, (int)L.npl, fr, fx, s);
@@ -2227,12 +2336,38 @@ int server_launch(fe_server *sv, fe_server::Lane &ln)
             d.qctr = qc + q++;
             launch_persist(L.N, true, dd, d, grid, s);
         }
-        launch_concat_batch(d, lists_d + L.pl, (int)L.npl, true, s);
         for (int dd = 0; dd < NDCLS; ++dd)
-            if (L.npld[dd])
+            if (L.npld[dd]) {
+                launch_concat_batch(d, lists_d + L.pld[dd], (int)L.npld[dd], true, s);
                 launch_persist_fixup(L.N, true, dd, d, lists_d + L.pld[dd], (int)L.npld[dd], s);
+            }
+        // deep-class groups: k_deep over each request's window
+        for (const GroupDesc &g : sv->groups) {
+            if (g.key % NDCLS != DEEP_CLS || g.key / NDCLS + 1 != L.N) continue;
+            for (int r = 0; r < R; ++r) {
+                // (rings sized at creation for the longest window fit any shorter one)
+                const DeepPlan dp = deep_plan(L.N, (int64_t)g.tiles * WAVE, g.dcap, bj[r].n,
+                                              (int64_t)ln.deepd.cap);
+                if (dp.bytes > (int64_t)ln.deepd.cap)
+                    return fail(c, FE_EINTERNAL, "deep rings exceed the lane's scratch");
+                DeepArgs a{};
+                a.ids = bj[r].ids;
+                a.ticks = bj[r].ticks;
+                a.n = bj[r].n;
+                a.pk = P<int>(sv->pk) + g.rec_base;
+                a.orig = P<int>(sv->origd) + (int64_t)g.tile_base * WAVE;
+                a.ring = P<int2>(ln.deepd);
+                a.out = bj[r].exact;
+                a.upper = bj[r].upper;
+                a.theta = bj[r].theta;
+                a.status = P<int>(ln.statd);
+                deep_launch(L.N, a, dp, (int64_t)g.tiles * WAVE, s);
+            }
+        }
     }
     HIPCHK(c, hipMemcpyAsync(ln.hout, ln.outd.p, (size_t)R * 2 * M * sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(ln.hout + (size_t)R * 2 * M, ln.statd.p, sizeof(int),
                              hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipEventRecord(ln.done, s));
     HIPCHK(c, hipGetLastError());
@@ -2253,10 +2388,14 @@ void server_loop(fe_server *sv)
             const hipError_t e = hipEventQuery(ln.done);
             if (e == hipErrorNotReady) continue;
             const int64_t now = steady_ns();
+            // the round's device status word (a failed device check fails the round)
+            const int bits = e == hipSuccess ? ln.hout[ln.reqs.size() * 2 * (size_t)sv->M] : 0;
             for (size_t r = 0; r < ln.reqs.size(); ++r) {
                 fe_server::Req *q = ln.reqs[r];
                 if (e != hipSuccess) {
                     q->status = FE_EDEVICE;
+                } else if (bits) {
+                    q->status = status_code(bits);
                 } else {
                     const int *u = ln.hout + r * 2 * (size_t)sv->M;
                     q->up.assign(u, u + sv->M);
@@ -2400,7 +2539,7 @@ extern "C" int fe_server_create(fe_ctx *c, const fe_server_config *cfg, const in
                 C.key.push_back(t);
                 if (k < N - 1) {
                     const int l = lov[(size_t)m * (nm - 1) + k], h = hiv[(size_t)m * (nm - 1) + k];
-                    if (l < 0 || l >= h || h >= TICK_LIMIT || h / (h - l + 1) >= 8)
+                    if (l < 0 || l >= h || h >= TICK_LIMIT)
                         return bail(fail(c, FE_EINVAL, "bad interval"));
                     W += h;
                     C.key.push_back(l);
@@ -2442,6 +2581,12 @@ extern "C" int fe_server_create(fe_ctx *c, const fe_server_config *cfg, const in
         if ((rc = ensure(c, sv->arr[a].ticks, cfg->capacity * sizeof(int)))) return bail(rc);
         sv->arr[a].hticks.reserve(std::min<int64_t>(cfg->capacity, 1 << 24));
     }
+    // deep-class rings: the largest any round needs (windows of up to capacity events)
+    int64_t deep_bytes = 0;
+    for (const GroupDesc &g : sv->groups)
+        if (g.key % NDCLS == DEEP_CLS)
+            deep_bytes = std::max(deep_bytes, deep_plan(g.key / NDCLS + 1, (int64_t)g.tiles * WAVE,
+                                                        g.dcap, (int)cfg->capacity).bytes);
     // lanes: stream, completion event, arena sized to the lane's budget
     const int64_t lane_budget = std::max<int64_t>(1, cfg->hbm_budget / cfg->max_inflight);
     const int64_t max_one = req_arena_bytes(sv, (int)cfg->capacity);
@@ -2455,7 +2600,10 @@ extern "C" int fe_server_create(fe_ctx *c, const fe_server_config *cfg, const in
         if ((rc = ensure(c, L.descd, (size_t)cfg->max_round * sv->ntiles * sizeof(TileDesc))))
             return bail(rc);
         if ((rc = ensure(c, L.jobsd, (size_t)cfg->max_round * sizeof(BJob)))) return bail(rc);
-        HIPCHK(c, hipHostMalloc((void **)&L.hout, (size_t)cfg->max_round * 2 * M * sizeof(int)));
+        if ((rc = ensure(c, L.statd, sizeof(int)))) return bail(rc);
+        if (deep_bytes > 0 && (rc = ensure(c, L.deepd, (size_t)deep_bytes))) return bail(rc);
+        HIPCHK(c, hipHostMalloc((void **)&L.hout,
+                                ((size_t)cfg->max_round * 2 * M + 1) * sizeof(int)));
     }
     sv->th = std::thread(server_loop, sv);
     *out = sv;
@@ -2602,7 +2750,7 @@ extern "C" int fe_server_destroy(fe_server *sv)
     (void)hipSetDevice(c->device);
     for (auto &L : sv->lanes) {
         if (L.s) (void)hipStreamSynchronize(L.s);
-        Buf *bs[] = {&L.arena, &L.outd, &L.descd, &L.jobsd};
+        Buf *bs[] = {&L.arena, &L.outd, &L.descd, &L.jobsd, &L.statd, &L.deepd};
         for (Buf *x : bs)
             if (x->p) (void)hipFree(x->p);
         if (L.hout) (void)hipHostFree(L.hout);

@@ -10,7 +10,12 @@ namespace fe {
 constexpr int WAVE = 64;
 constexpr int NMAX = 8;          // largest episode size
 constexpr int KMAX = 16;         // slot-table entries kept per (candidate, segment)
-constexpr int NDCLS = 4;         // list-depth classes of the exact machine: 1,2,4,8 windows
+// List-depth classes of the exact machine: classes 0..3 keep 1, 2, 4, 8
+// windows per list in registers; class DEEP_CLS holds the candidates with a
+// hop whose window bound hi/(hi-lo+1)+1 exceeds 8, whose lists are ring
+// buffers in device memory (k_deep).
+constexpr int NDCLS = 5;
+constexpr int DEEP_CLS = 4;
 constexpr int NKEYS = NMAX * NDCLS;
 constexpr int TICK_LIMIT = 1 << 30;
 constexpr int WPB = 4;           // waves per block in the Map kernels
@@ -22,6 +27,13 @@ constexpr int ST_BADCAND = 4;
 constexpr int ST_INTERNAL = 8;
 
 inline constexpr int dcls_depth(int c) { return 1 << c; }
+// list-depth class of a candidate whose largest window bound is `bound`
+__host__ __device__ inline int depth_class(int bound)
+{
+    return bound <= 1 ? 0 : bound <= 2 ? 1 : bound <= 4 ? 2 : bound <= 8 ? 3 : DEEP_CLS;
+}
+// live windows of one exact list for a hop (lo, hi]: hi/(hi-lo+1)+1
+__host__ __device__ inline int window_bound(int lo, int hi) { return hi / (hi - lo + 1) + 1; }
 // ints in one packed tile record: types[N][64], lo[N-1][64], hi[N-1][64]
 inline constexpr int rec_ints(int N) { return (3 * N - 2) * WAVE; }
 
@@ -83,6 +95,28 @@ struct BatchDev {
     int sparse;  // per-type dispatch for the bulk of each item
 };
 
+// Exact count of candidates of the deep class: one wave per tile over the
+// whole stream, each lane's N-1 lists as rings of `cap` windows in `ring`.
+// A launch covers the group's flattened lanes [g0, g1) (lane index
+// tile*64+lane, relative to pk/orig); ring holds (g1-g0)*(N-1)*cap windows.
+struct DeepArgs {
+    const int *ids, *ticks;
+    int n;
+    const int *pk;     // group's first record
+    const int *orig;   // [tiles*64] candidate index, -1 = padding
+    int64_t g0, g1;    // active lanes of this launch
+    int2 *ring;
+    int cap;
+    int *out;          // [M] exact counts, by candidate index
+    const int *upper;  // optional: lanes with upper[o] < theta write -1 (pruned)
+    int theta;
+    int from;                    // incremental count (count_io != null): events
+    int *count_io, *last_io;     //   before `from` were counted by earlier calls
+    int *status;
+};
+// window rings one deep launch may hold by default (bytes)
+constexpr int64_t DEEP_SCRATCH = (int64_t)256 << 20;
+
 // launchers (fe_kernels.hip)
 void launch_fill(int *p, int v, int64_t n, hipStream_t s);
 void launch_validate(const int *ids, const int *ticks, int n, int num_types,
@@ -106,6 +140,7 @@ void launch_fixup(int N, bool exact, int dcls, const MapGroup &g, hipStream_t s)
 void launch_persist(int N, bool exact, int dcls, const BatchDev &b, int grid, hipStream_t s);
 void launch_resume(int N, bool exact, int dcls, const MapGroup &g, int from, int *count_io,
                    int *last_io, hipStream_t s);
+void launch_deep(int N, const DeepArgs &a, hipStream_t s);
 void launch_build_rec(const int *key, int m, const int *orig, int tiles, int *rec, int *tileW,
                       hipStream_t s);
 // Run-aligned tiling of a level on the device (fe_tiling.hip).  scratch:

@@ -47,9 +47,11 @@ void launch_validate(const int *ids, const int *ticks, int n, int num_types, int
 }
 
 // ------------------------------------------------------------------ candidate grouping
-// Key of a candidate: (N-1)*NDCLS + depth class; -1 if the candidate is invalid.
+// Key of a candidate: (N-1)*NDCLS + list-depth class (0 for the relaxed
+// counter); -1 if the candidate is invalid.  W_out: sum of hi; B_out: the
+// largest window bound of its hops (the ring capacity of the deep class).
 __device__ int cand_key(const int *types, const int *len, const int *lo, const int *hi,
-                        int nmax, int m, int num_types, int exact, int *W_out)
+                        int nmax, int m, int num_types, int exact, int *W_out, int *B_out)
 {
     const int N = len[m];
     if (N < 1 || N > nmax) return -1;
@@ -64,20 +66,13 @@ __device__ int cand_key(const int *types, const int *len, const int *lo, const i
         const int l = lo[ib + k], h = hi[ib + k];
         if (l < 0 || l >= h || h >= TICK_LIMIT) return -1;
         W += h;
-        const int b = h / (h - l + 1) + 1;
+        const int b = window_bound(l, h);
         bound = b > bound ? b : bound;
     }
     if (W >= TICK_LIMIT) return -1;
-    int dc = 0;
-    if (exact) {
-        if (bound <= 1) dc = 0;
-        else if (bound <= 2) dc = 1;
-        else if (bound <= 4) dc = 2;
-        else if (bound <= 8) dc = 3;
-        else return -1;
-    }
     *W_out = (int)W;
-    return (N - 1) * NDCLS + dc;
+    *B_out = bound;
+    return (N - 1) * NDCLS + (exact ? depth_class(bound) : 0);
 }
 
 // Wave-aggregated "reserve one slot in counter[key]" -- returns the rank of
@@ -107,8 +102,9 @@ __device__ int wave_reserve(int key, int *counter)
     return pos;
 }
 
-// hist[key] += candidates with that key; hist[NKEYS + key] = max W among them;
-// bcnt[key * nb + block] = the block's candidates with that key.
+// hist[key] += candidates with that key; hist[NKEYS + key] = max W among
+// them; hist[2*NKEYS + key] = their largest window bound; bcnt[key * nb +
+// block] = the block's candidates with that key.
 __global__ void k_prep_count(const int *types, const int *len, const int *lo, const int *hi,
                              int nmax, const int *sel, const int *nsel, int M, int num_types,
                              int exact, int *keys, int *hist, int *status, int *bcnt, int nb)
@@ -119,10 +115,10 @@ __global__ void k_prep_count(const int *types, const int *len, const int *lo, co
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = __lane_id();
     const int lim = nsel ? *nsel : M;
-    int key = -1, W = 0;
+    int key = -1, W = 0, B = 1;
     if (i < lim) {
         const int m = sel ? sel[i] : i;
-        key = cand_key(types, len, lo, hi, nmax, m, num_types, exact, &W);
+        key = cand_key(types, len, lo, hi, nmax, m, num_types, exact, &W, &B);
         if (key < 0) atomicOr(status, ST_BADCAND);
         keys[i] = key;
     }
@@ -133,16 +129,18 @@ __global__ void k_prep_count(const int *types, const int *len, const int *lo, co
         const int leader = __ffsll((long long)act) - 1;
         const int k0 = __shfl(key, leader);
         const bool mine = pending && key == k0;
-        int wm = mine ? W : 0;
+        int wm = mine ? W : 0, bm = mine ? B : 0;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
-            const int o = __shfl_xor(wm, off);
+            const int o = __shfl_xor(wm, off), ob = __shfl_xor(bm, off);
             wm = o > wm ? o : wm;
+            bm = ob > bm ? ob : bm;
         }
         const int cntk = __popcll(__ballot(mine));
         if (lane == leader) {
             atomicAdd(&hist[k0], cntk);
             atomicMax(&hist[NKEYS + k0], wm);
+            atomicMax(&hist[2 * NKEYS + k0], bm);
             atomicAdd(&sc[k0], cntk);
         }
         pending = pending && !mine;
@@ -309,6 +307,29 @@ void launch_resume_n5(bool, int, const MapGroup &, int, int *, int *, hipStream_
 void launch_resume_n6(bool, int, const MapGroup &, int, int *, int *, hipStream_t);
 void launch_resume_n7(bool, int, const MapGroup &, int, int *, int *, hipStream_t);
 void launch_resume_n8(bool, int, const MapGroup &, int, int *, int *, hipStream_t);
+
+void launch_deep_n1(const DeepArgs &, hipStream_t);
+void launch_deep_n2(const DeepArgs &, hipStream_t);
+void launch_deep_n3(const DeepArgs &, hipStream_t);
+void launch_deep_n4(const DeepArgs &, hipStream_t);
+void launch_deep_n5(const DeepArgs &, hipStream_t);
+void launch_deep_n6(const DeepArgs &, hipStream_t);
+void launch_deep_n7(const DeepArgs &, hipStream_t);
+void launch_deep_n8(const DeepArgs &, hipStream_t);
+
+void launch_deep(int N, const DeepArgs &a, hipStream_t s)
+{
+    switch (N) {
+    case 1: return launch_deep_n1(a, s);
+    case 2: return launch_deep_n2(a, s);
+    case 3: return launch_deep_n3(a, s);
+    case 4: return launch_deep_n4(a, s);
+    case 5: return launch_deep_n5(a, s);
+    case 6: return launch_deep_n6(a, s);
+    case 7: return launch_deep_n7(a, s);
+    default: return launch_deep_n8(a, s);
+    }
+}
 
 void launch_resume(int N, bool exact, int dcls, const MapGroup &g, int from, int *count_io,
                    int *last_io, hipStream_t s)

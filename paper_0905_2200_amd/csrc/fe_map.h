@@ -1155,6 +1155,213 @@ __global__ __launch_bounds__(WAVE *WPB) void k_persist_fixup(BatchDev b, const i
     if (f) (EXACT ? jb.exact : jb.upper)[o] = cnt;
 }
 
+// Exact lists of the deep class (a hop with more than 8 live windows, e.g. a
+// narrow interval far from 0 such as (190, 200] ticks).  The same windows as
+// Exact<N, D> -- the union of [e+lo+1, e+hi] over the list's entries e, in
+// push order, touching windows merged -- kept as a ring of `cap` windows per
+// list in device memory, with the oldest kept window and the newest end in
+// registers.  Windows that ended before the current tick are dropped from
+// the front (ticks never decrease, so they can pass no later test); a hop
+// test then only looks at the front window: live windows are disjoint and
+// ordered, so if the tick is before the front one it is before all.  Live
+// windows of list k end at or after t, so their last entries lie in
+// [t-hi, t]: there are at most hi/(hi-lo+1)+1 of them and at most as many as
+// events in that range, which sizes cap (overflow sets ST_INTERNAL).
+template <int N> struct ExactDeep {
+    static constexpr int L = N > 1 ? N - 1 : 1;
+    int2 *w;       // this lane's rings: list k at w[k*cap ...]
+    unsigned cap;
+    unsigned head[L], cnt[L];
+    int fa[L], fb[L];  // front window
+    int nb[L];         // end of the newest window
+    __device__ __forceinline__ void bind(int2 *ring, int c)
+    {
+        w = ring;
+        cap = (unsigned)c;
+    }
+    __device__ __forceinline__ void reset()
+    {
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            head[k] = 0;
+            cnt[k] = 0;
+            fa[k] = EMPTY;
+            fb[k] = GONE;
+            nb[k] = GONE;
+        }
+    }
+    __device__ __forceinline__ int end_of(int k) const { return nb[k]; }
+    __device__ __forceinline__ void drop_dead(int k, int t)
+    {
+        while (cnt[k] != 0 && fb[k] < t) {
+            head[k] = head[k] + 1 == cap ? 0 : head[k] + 1;
+            if (--cnt[k] != 0) {
+                const int2 v = w[(int64_t)k * cap + head[k]];
+                fa[k] = v.x;
+                fb[k] = v.y;
+            } else {
+                fa[k] = EMPTY;
+                fb[k] = GONE;
+                nb[k] = GONE;
+            }
+        }
+    }
+    __device__ __forceinline__ bool hit(int k, int t)
+    {
+        drop_dead(k, t);
+        return cnt[k] != 0 && t >= fa[k];
+    }
+    __device__ __forceinline__ void push(int k, int t, int lo, int hi, int *status)
+    {
+        const int a = t + lo + 1, b = t + hi;
+        drop_dead(k, t);
+        if (cnt[k] != 0 && nb[k] >= a - 1) {
+            // overlaps or abuts the newest window: extend it
+            unsigned tail = head[k] + cnt[k] - 1;
+            if (tail >= cap) tail -= cap;
+            w[(int64_t)k * cap + tail].y = b;
+            nb[k] = b;
+            if (cnt[k] == 1) fb[k] = b;
+            return;
+        }
+        if (cnt[k] == cap) {
+            atomicOr(status, ST_INTERNAL);
+            return;
+        }
+        unsigned tail = head[k] + cnt[k];
+        if (tail >= cap) tail -= cap;
+        w[(int64_t)k * cap + tail] = make_int2(a, b);
+        if (cnt[k]++ == 0) {
+            fa[k] = a;
+            fb[k] = b;
+        }
+        nb[k] = b;
+    }
+    // Node loop of Algorithm 1 for one event (tested against the state
+    // before the event, nodes N..1); true = completion at node N.
+    __device__ __forceinline__ bool step(int e, int t, const Cand<N> &c, int *status)
+    {
+        if constexpr (N == 1) {
+            return e == c.ty[0];
+        } else {
+            bool comp = false;
+            if (e == c.ty[N - 1]) comp = hit(N - 2, t);
+            if (comp) return true;  // the lists are cleared anyway
+#pragma unroll
+            for (int i = N - 2; i >= 1; --i)
+                if (e == c.ty[i])
+                    if (hit(i - 1, t)) push(i, t, c.lo[i], c.hi[i], status);
+            if (e == c.ty[0]) push(0, t, c.lo[0], c.hi[0], status);
+            return false;
+        }
+    }
+};
+
+// Whole-stream exact count of one chunk of a deep-class group: one wave per
+// tile, lanes outside [g0, g1) idle.  Per-type dispatch lane by lane: in each
+// block of 64 events a lane steps only the events whose type hash is one of
+// its nodes' (the others leave its machine unchanged).  In the incremental
+// form each lane starts after max(last completion, lam - 1) as in k_resume.
+template <int N>
+__global__ __launch_bounds__(WAVE *WPB) void k_deep(DeepArgs a)
+{
+    __shared__ unsigned long long s_tm[WPB][WAVE];
+    __shared__ int2 s_ev[WPB][WAVE];
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    const int64_t tile = a.g0 / WAVE + uniform(blockIdx.x * WPB + wv);
+    if (tile * WAVE >= a.g1) return;
+    const int64_t gl = tile * WAVE + lane;
+    const int o = a.orig[gl];
+    bool on = o >= 0 && gl >= a.g0 && gl < a.g1;
+    if (on && a.upper && a.upper[o] < a.theta) {
+        a.out[o] = -1;
+        on = false;
+    }
+    Cand<N> cd;
+    load_cand<N>(cd, a.pk + tile * rec_ints(N), lane);
+    ExactDeep<N> m;
+    m.bind(a.ring + (on ? (gl - a.g0) * (int64_t)(N > 1 ? N - 1 : 1) * a.cap : 0), a.cap);
+    m.reset();
+    const int n = a.n;
+    int st = on ? 0 : n;  // this lane's first event
+    int prev = -1;
+    if (on && a.count_io) {
+        int W = 0;
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) W += cd.hi[k];
+        st = n;
+        if (a.from < n) {
+            const int x = a.ticks[a.from] - W;
+            int lo = 0, hi = a.from;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (a.ticks[mid] < x) lo = mid + 1;
+                else hi = mid;
+            }
+            prev = a.last_io[o];
+            const int r1 = prev + 1 < 0 ? 0 : (prev + 1 > a.from ? a.from : prev + 1);
+            st = r1 > lo ? r1 : lo;
+        }
+    }
+    int smin = st;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int x = __shfl_xor(smin, off);
+        smin = x < smin ? x : smin;
+    }
+    smin = uniform(smin);
+    int cnt = 0, lastc = -1;
+    unsigned long long *tm = s_tm[wv];
+    int2 *evs = s_ev[wv];
+    const int lane4 = lane * 4;
+    for (int cb = smin; cb < n; cb += EV_CHUNK) {
+        const int ce = n - cb > EV_CHUNK ? cb + EV_CHUNK : n;
+        const EvBuf eb(a.ids, a.ticks, cb, ce);
+        int nid, ntk;
+        eb.load(0, lane4, nid, ntk);
+        for (int i = cb; i < ce; i += WAVE) {
+            const int id = nid, tk = ntk;
+            eb.load(i - cb + WAVE, lane4, nid, ntk);
+            tm[lane] = 0;
+            evs[lane] = make_int2(id, tk);
+            if (lane < ce - i) atomicOr(&tm[id & 63], 1ull << lane);
+            unsigned long long ml = 0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) ml |= tm[cd.ty[q] & 63];
+            // positions before this lane's start
+            if (st > i) ml = st - i >= WAVE ? 0 : ml & ~((1ull << (st - i)) - 1ull);
+            if (!on) ml = 0;
+            while (ml) {
+                const int pos = (int)__builtin_ctzll(ml);
+                ml &= ml - 1ull;
+                const int2 et = evs[pos];
+                if (m.step(et.x, et.y, cd, a.status)) {
+                    m.reset();
+                    ++cnt;
+                    lastc = i + pos;
+                }
+            }
+        }
+    }
+    if (on) {
+        if (a.count_io) {
+            a.count_io[o] += cnt;
+            a.last_io[o] = lastc >= 0 ? lastc : prev;
+        } else {
+            a.out[o] = cnt;
+        }
+    }
+}
+
+template <int N> void deep_n(const DeepArgs &a, hipStream_t s)
+{
+    const int64_t t0 = a.g0 / WAVE, t1 = (a.g1 + WAVE - 1) / WAVE;
+    if (t1 <= t0) return;
+    hipLaunchKernelGGL((k_deep<N>), dim3((unsigned)((t1 - t0 + WPB - 1) / WPB)), dim3(WAVE * WPB),
+                       0, s, a);
+}
+
 template <int N, bool EXACT, int D>
 void persist_n(const BatchDev &b, int grid, const int *ctiles, int nct, hipStream_t s, bool fix)
 {

@@ -16,4 +16,5 @@ void launch_resume_n4(bool exact, int dcls, const MapGroup &g, int from, int *co
 {
     resume_dispatch_n<4>(exact, dcls, g, from, count_io, last_io, s);
 }
+void launch_deep_n4(const DeepArgs &a, hipStream_t s) { deep_n<4>(a, s); }
 }  // namespace fe

@@ -16,4 +16,5 @@ void launch_resume_n5(bool exact, int dcls, const MapGroup &g, int from, int *co
 {
     resume_dispatch_n<5>(exact, dcls, g, from, count_io, last_io, s);
 }
+void launch_deep_n5(const DeepArgs &a, hipStream_t s) { deep_n<5>(a, s); }
 }  // namespace fe

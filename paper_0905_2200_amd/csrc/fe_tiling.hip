@@ -29,11 +29,10 @@ __device__ __forceinline__ int key_dcls(const int *k, int m)
 {
     int bound = 1;
     for (int j = 0; j < m - 1; ++j) {
-        const int lo = k[3 * j + 1], hi = k[3 * j + 2];
-        const int b = hi / (hi - lo + 1) + 1;
+        const int b = window_bound(k[3 * j + 1], k[3 * j + 2]);
         bound = b > bound ? b : bound;
     }
-    return bound <= 1 ? 0 : bound <= 2 ? 1 : bound <= 4 ? 2 : 3;
+    return depth_class(bound);
 }
 
 // cls[i] = list-depth class of a kept candidate (0 for the relaxed pass),
