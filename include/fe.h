@@ -155,6 +155,27 @@ int fe_count(fe_ctx *ctx, const int32_t *ids, const int32_t *ticks, int64_t n,
              const int32_t *lo, const int32_t *hi, int32_t M, int32_t nmax,
              int mode, int32_t *counts_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fe_count
+ * with the same arguments, semantics and results, whose workspace (candidate
+ * grouping, packed tiles, segment tables, window rings) is carved from a
+ * fixed 64 MiB device array that the library holds on each device until the
+ * process ends.  It calls no hipMalloc, hipFree or allocating library
+ * routine (the context's pinned staging and status word, made by
+ * fe_create, are reused).  Limit: inputs whose whole-stream workspace
+ * (about 4 B per candidate, (3*nmax-2)*4 B per candidate for the packed
+ * table, and 1 B per event) exceeds 64 MiB are rejected with FE_ENOMEM
+ * before any work is enqueued; the segment count is lowered until the
+ * segment tables fit what is left.  Every call on one device shares that
+ * device's array and leaves its contents behind: calls that overlap on one
+ * device -- from any context -- race, so order them (e.g. one stream, or
+ * fe_sync between them).  FE_EDEVICE if the array could not be located on
+ * the device at fe_create.  Synchronises once (candidate grouping). */
+int fe_count_noalloc(fe_ctx *ctx, const int32_t *ids, const int32_t *ticks, int64_t n,
+                     int32_t num_types, const int32_t *types, const int32_t *len,
+                     const int32_t *lo, const int32_t *hi, int32_t M, int32_t nmax,
+                     int mode, int32_t *counts_out);
+
 /* Incremental counting of a growing recording, processed in consecutive
  * partitions (the paper's real-time "chip-on-chip" use, Sec. 1 and Sec. 7).
  * ids/ticks[0, n) on the device are the stream so far; the events before

@@ -81,6 +81,15 @@ template <class T, class U> bool operator==(const NoInit<T> &, const NoInit<U> &
 template <class T, class U> bool operator!=(const NoInit<T> &, const NoInit<U> &) { return false; }
 typedef std::vector<int, NoInit<int>> ivec;
 
+// Fixed device scratch of the no-allocation entry point (fe_count_noalloc):
+// each device holds its own copy until the process ends.  Host code never
+// uses this name as an address: fe_create looks up this device's copy with
+// hipGetSymbolAddress, once per device, and keeps the pointer.
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+std::mutex g_fixed_mu;
+std::map<int, char *> g_fixed;  // device -> its copy of scratch
+
 double now_ms()
 {
     return std::chrono::duration<double, std::milli>(
@@ -101,6 +110,11 @@ struct fe_ctx {
     Buf keys, hist, wmax, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
     Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn, mkey, tscr, tinfo, mfk, mfo, mfsel, pbc;
     Buf deep;  // window rings of the deep-class exact launches
+    // This device's copy of the fixed scratch array (fe_count_noalloc), and
+    // while such a call runs, the bump arena its workspace is carved from.
+    char *fixed = nullptr;
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
     // host arrays of the mining driver, kept for reuse (large ones are pinned)
     ivec keypool, lanepool, uphpool, orderpool;
     int *host = nullptr;  // pinned host staging for small readbacks
@@ -146,6 +160,18 @@ int fail(fe_ctx *c, int code, const char *fmt, ...)
 int ensure(fe_ctx *c, Buf &b, size_t bytes)
 {
     if (bytes == 0) bytes = 4;
+    if (c->arena) {
+        // no-allocation call: carve from the fixed scratch; never allocate or free
+        if (b.p && b.cap >= bytes) return FE_OK;
+        const size_t a = (bytes + 255) & ~(size_t)255;
+        if (c->arena_used + a > c->arena_cap)
+            return fail(c, FE_ENOMEM, "the call needs more than the %zu-byte fixed scratch",
+                        c->arena_cap);
+        b.p = c->arena + c->arena_used;
+        b.cap = a;
+        c->arena_used += a;
+        return FE_OK;
+    }
     if (b.cap >= bytes) return FE_OK;
     if (b.p) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -170,6 +196,7 @@ int ensure(fe_ctx *c, Buf &b, size_t bytes)
 int ensure_host(fe_ctx *c, size_t ints)
 {
     if (c->host_cap >= ints) return FE_OK;
+    if (c->arena) return fail(c, FE_EINTERNAL, "pinned staging too small for a no-allocation call");
     if (c->host) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         HIPCHK(c, hipHostFree(c->host));
@@ -230,7 +257,8 @@ struct KTimer {
     fe_ctx *c;
     bool on;
     fe_ctx::Pending p;
-    KTimer(fe_ctx *c_, const char *name, double ee) : c(c_), on(c_->param[FE_PARAM_TIMING] != 0)
+    KTimer(fe_ctx *c_, const char *name, double ee)
+        : c(c_), on(c_->param[FE_PARAM_TIMING] != 0 && !c_->arena)
     {
         if (!on) return;
         p.name = name;
@@ -384,7 +412,9 @@ int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo 
         if (exact && dcls == DEEP_CLS) {
             // lists beyond 8 windows: rings in device memory, whole stream
             const int64_t lanes = (int64_t)tiles * WAVE;
-            const DeepPlan dp = deep_plan(N, lanes, gd.dcap, si.n);
+            const int64_t budget =
+                c->arena ? (int64_t)(c->arena_cap - c->arena_used) / 256 * 256 : DEEP_SCRATCH;
+            const DeepPlan dp = deep_plan(N, lanes, gd.dcap, si.n, std::max<int64_t>(budget, 1));
             if ((rc = ensure(c, c->deep, (size_t)dp.bytes))) return rc;
             DeepArgs a{};
             a.ids = ids;
@@ -422,6 +452,18 @@ int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo 
         g.tbl = nullptr;
         g.flags = nullptr;
         g.P = rs ? 1 : choose_P(c, tiles, si, gd.wmax, N);
+        if (c->arena) {
+            // no-allocation call: as many segments as the fixed scratch's
+            // remainder holds the tables of (P = 1 needs none)
+            const size_t avail = c->arena_cap - c->arena_used;
+            auto need = [&](int64_t P) {
+                const auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+                return al((size_t)tiles * (P + 1) * sizeof(int)) +
+                       al((size_t)P * tiles * WAVE * KMAX * sizeof(int2)) +
+                       al((size_t)tiles * WAVE * sizeof(int));
+            };
+            while (g.P > 1 && need(g.P) > avail) g.P /= 2;
+        }
         g.sparse = c->param[FE_PARAM_TYPE_DISPATCH] != 0;
         g.hashx = si.num_types <= 64;
         c->stats.map_launches++;
@@ -682,6 +724,18 @@ extern "C" int fe_create(int device, void *hip_stream, fe_ctx **out)
         return FE_ENOMEM;
     }
     launch_fill(P<int>(c->status), 0, 1, c->stream);
+    {
+        // this device's copy of the fixed scratch (with the device current)
+        std::lock_guard<std::mutex> lk(g_fixed_mu);
+        auto it = g_fixed.find(device);
+        if (it == g_fixed.end()) {
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e == hipSuccess && p) it = g_fixed.emplace(device, (char *)p).first;
+            else (void)hipGetLastError();
+        }
+        if (it != g_fixed.end()) c->fixed = it->second;
+    }
     *out = c;
     return FE_OK;
 }
@@ -814,6 +868,59 @@ extern "C" int fe_count(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int
     if ((rc = stream_info(c, ids, ticks, (int)n, num_types, si))) return rc;
     CandIn cin{types, len, lo, hi, nmax};
     rc = count_impl(c, ids, ticks, si, num_types, cin, M, mode, counts_out);
+    c->stats.last_call_ms = now_ms() - t0;
+    return rc;
+}
+
+extern "C" int fe_count_noalloc(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int64_t n,
+                                int32_t num_types, const int32_t *types, const int32_t *len,
+                                const int32_t *lo, const int32_t *hi, int32_t M, int32_t nmax,
+                                int mode, int32_t *counts_out)
+{
+    int rc;
+    const double t0 = now_ms();
+    if ((rc = check_common(c, ids, ticks, n, num_types))) return rc;
+    if ((rc = check_cands(c, types, len, lo, hi, M, nmax))) return rc;
+    if (mode != FE_EXACT && mode != FE_RELAXED) return fail(c, FE_EINVAL, "bad mode");
+    if (M > 0 && !counts_out) return fail(c, FE_EINVAL, "null output");
+    if (!c->fixed) return fail(c, FE_EDEVICE, "no fixed scratch on device %d", c->device);
+    // the workspace of a whole-stream count (P = 1, no deep rings) must fit
+    const auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const int64_t tiles_max = ((int64_t)M + WAVE - 1) / WAVE + NKEYS;
+    const int64_t nbc = (int64_t)NKEYS * ((M + 255) / 256);
+    const size_t need = al((size_t)M * 4) + al(3 * NKEYS * 4) +
+                        al((size_t)(2 * nbc + scan_scratch_ints(nbc)) * 4) +
+                        al((size_t)tiles_max * rec_ints(nmax) * 4) +
+                        al((size_t)tiles_max * WAVE * 4) + al((size_t)tiles_max * 4) +
+                        al((size_t)((n + 7) / 8) * 8);
+    if (need > NOALLOC_BYTES)
+        return fail(c, FE_ENOMEM,
+                    "%d candidates over %lld events need up to %zu bytes of workspace; the "
+                    "fixed scratch holds %zu (use fe_count)",
+                    M, (long long)n, need, NOALLOC_BYTES);
+    HIPCHK(c, hipSetDevice(c->device));
+    c->stats = fe_stats{};
+    // every workspace buffer of the call comes from the fixed scratch; the
+    // context's own buffers are set aside and restored afterwards
+    Buf *ws[] = {&c->keys, &c->hist, &c->pbc, &c->pk,  &c->orig, &c->tileW,
+                 &c->cmask, &c->lam, &c->tbl, &c->flags, &c->deep};
+    constexpr int NWS = (int)(sizeof ws / sizeof ws[0]);
+    Buf saved[NWS];
+    for (int i = 0; i < NWS; ++i) {
+        saved[i] = *ws[i];
+        *ws[i] = Buf{};
+    }
+    c->arena = c->fixed;
+    c->arena_cap = NOALLOC_BYTES;
+    c->arena_used = 0;
+    StreamInfo si;
+    rc = stream_info(c, ids, ticks, (int)n, num_types, si);
+    if (!rc) {
+        CandIn cin{types, len, lo, hi, nmax};
+        rc = count_impl(c, ids, ticks, si, num_types, cin, M, mode, counts_out);
+    }
+    c->arena = nullptr;
+    for (int i = 0; i < NWS; ++i) *ws[i] = saved[i];
     c->stats.last_call_ms = now_ms() - t0;
     return rc;
 }

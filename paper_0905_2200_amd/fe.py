@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "FE_OK", 1: "FE_EINVAL", 2: "FE_ENOMEM", 3: "FE_EDEVICE",
                 4: "FE_EUNSORTED", 5: "FE_ERANGE", 6: "FE_EBUSY", 7: "FE_EINTERNAL"}
 
 EXPORTS = ["fe_create", "fe_destroy", "fe_last_error", "fe_sync", "fe_set_param",
-           "fe_get_param", "fe_validate", "fe_count", "fe_count_resume", "fe_count_two_pass",
+           "fe_get_param", "fe_validate", "fe_count", "fe_count_noalloc", "fe_count_resume",
+           "fe_count_two_pass",
            "fe_mine",
            "fe_result_free", "fe_get_stats", "fe_get_kernel_stats", "fe_reset_kernel_stats",
            "fe_batch_create", "fe_batch_run", "fe_batch_autotune", "fe_batch_set_tuning",
@@ -125,6 +126,8 @@ def lib():
         "fe_get_param": ([CTX, ctypes.c_int, ctypes.POINTER(I64)], ctypes.c_int),
         "fe_validate": ([CTX, V, V, I64, I32], ctypes.c_int),
         "fe_count": ([CTX, V, V, I64, I32, V, V, V, V, I32, I32, ctypes.c_int, V], ctypes.c_int),
+        "fe_count_noalloc": ([CTX, V, V, I64, I32, V, V, V, V, I32, I32, ctypes.c_int, V],
+                             ctypes.c_int),
         "fe_count_two_pass": ([CTX, V, V, I64, I32, V, V, V, V, I32, I32, I32, V, V, V],
                               ctypes.c_int),
         "fe_count_resume": ([CTX, V, V, I64, I32, V, V, V, V, I32, I32, ctypes.c_int, I64, V, V],
@@ -296,6 +299,18 @@ class Context:
         rc = self._call(lib().fe_count, self.h, _ptr(ids), _ptr(ticks), ids.numel(), int(num_types),
                             _ptr(c["types"]), _ptr(c["len"]), _ptr(c["lo"]), _ptr(c["hi"]),
                             M, c["nmax"], int(mode), _ptr(out))
+        self._check(rc)
+        return out[:M]
+
+    def count_noalloc(self, ids, ticks, num_types, cand, mode, out):
+        """fe_count_noalloc: fe_count whose workspace is the library's fixed
+        device scratch (no device allocation in the call); `out` is a
+        caller-allocated device int32 tensor of at least M entries."""
+        c = cand if "nmax" in cand and hasattr(cand["types"], "data_ptr") else self.cand_tensors(cand)
+        M = c["M"]
+        rc = self._call(lib().fe_count_noalloc, self.h, _ptr(ids), _ptr(ticks), ids.numel(),
+                        int(num_types), _ptr(c["types"]), _ptr(c["len"]), _ptr(c["lo"]),
+                        _ptr(c["hi"]), M, c["nmax"], int(mode), _ptr(out))
         self._check(rc)
         return out[:M]
 
