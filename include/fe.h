@@ -98,25 +98,51 @@ typedef enum fe_param {
                                 through every lane.  Read at each count call,
                                 at fe_batch_create and at each server round.
                                 Counts are identical either way.              */
-    FE_PARAM_CROSSOVER_A = 6, /* hybrid rule (Algorithm 2, Eq. 2): a group of  */
-    FE_PARAM_CROSSOVER_B = 7, /* tiles >= A/N + B tiles of N-node candidates is
-                                counted whole-stream (P = 1), a smaller one by
-                                MapConcatenate with P >= 2.  Defaults 548 and
-                                12651: fitted to crossovers measured on a 256-CU
-                                MI355X (python -m paper_0905_2200_amd.crossover).
-                                Ignored when FE_PARAM_SEGMENTS > 0.           */
-    FE_PARAM_ELIMINATION = 8, /* fe_mine: 1 (default) = two-pass elimination
+    FE_PARAM_CROSSOVER_A = 6, /* hybrid rule (Algorithm 2, Eq. 2), exact       */
+    FE_PARAM_CROSSOVER_B = 7, /* counter: a group of tiles >= A/N + B tiles of
+                                N-node candidates is counted whole-stream
+                                (P = 1), a smaller one by MapConcatenate with
+                                P >= 2.  Defaults -8136 and 19504 (A may be
+                                negative): the least-squares fit to crossovers
+                                measured on a 256-CU MI355X (python -m
+                                paper_0905_2200_amd.crossover).  Ignored when
+                                FE_PARAM_SEGMENTS > 0.                        */
+    FE_PARAM_ELIMINATION = 8, /* fe_mine, per level: 1 = two-pass elimination
                                 (Algorithm 4: relaxed pass, prune, exact pass
                                 on the survivors); 0 = one pass of Algorithm 1
-                                over every candidate (upper reported as -1).
-                                The frequent episodes and exact counts are the
-                                same either way.                              */
-    FE_PARAM_HOST_TILING = 9  /* fe_mine: 0 (default) = each level's
+                                over every candidate (upper reported as -1);
+                                2 (default) = decided per level: levels of
+                                fewer than FE_PARAM_SAMPLE_MIN candidates take
+                                two passes; for larger ones the relaxed pass
+                                first runs on a sample (every 64th block of 64
+                                consecutive candidates) and two passes are
+                                taken when the sampled survivor fraction s
+                                satisfies s < 1 - FE_PARAM_PASS1_COST/1000
+                                (then the relaxed pass costs less than it
+                                saves), else one.  The frequent episodes and
+                                exact counts are the same either way.          */
+    FE_PARAM_HOST_TILING = 9, /* fe_mine: 0 (default) = each level's
                                 candidates are pruned and tiled on the device
                                 (sibling runs whole, by list-depth class);
                                 1 = the same tiling on the host (the relaxed
                                 counts are copied back and the lane assignment
-                                uploaded).  Same tiles, same results.         */
+                                uploaded).  Same tiles, same results.  The
+                                per-level decision of FE_PARAM_ELIMINATION = 2
+                                needs device tiling; with host tiling it takes
+                                two passes.                                    */
+    FE_PARAM_KEEP_CANDIDATES = 10, /* fe_mine: 1 = also return every
+                                candidate of each level with its counts
+                                (fe_level.all_*); 0 (default) = the frequent
+                                episodes only                                  */
+    FE_PARAM_CROSSOVER_A_RELAXED = 11, /* the hybrid rule's A and B for the  */
+    FE_PARAM_CROSSOVER_B_RELAXED = 12, /* relaxed counter (Algorithm 3);
+                                defaults 9232 and 5798 (same fit)             */
+    FE_PARAM_PASS1_COST = 13, /* cost of the relaxed pass per candidate, in
+                                thousandths of the exact pass's (default 800,
+                                measured on the mining workload's levels 3
+                                and 4); used by FE_PARAM_ELIMINATION = 2      */
+    FE_PARAM_SAMPLE_MIN = 14  /* smallest level sampled by FE_PARAM_ELIMINATION
+                                = 2 (default 131072 candidates)                */
 } fe_param;
 
 typedef struct fe_ctx fe_ctx;
@@ -223,6 +249,19 @@ typedef struct fe_level {
     int32_t *exact;       /* [n_frequent] exact counts                      */
     double gen_ms;        /* host candidate generation time                 */
     double count_ms;      /* device counting time (both passes)             */
+    int32_t passes;       /* 2: relaxed pass, elimination, exact pass on the
+                             survivors (Algorithm 4); 1: exact pass only
+                             (upper = -1, n_survivors = n_candidates)       */
+    int64_t sample_n;     /* candidates of the relaxed sample that decided
+                             the level's passes (0: none was taken)         */
+    int64_t sample_kept;  /* of which survived (upper >= theta)             */
+    /* With FE_PARAM_KEEP_CANDIDATES = 1, every candidate of the level in
+     * generation order (n_candidates entries each; NULL otherwise): */
+    int32_t *all_types;   /* [n_candidates * level]                         */
+    int32_t *all_lo;      /* [n_candidates * (level-1)]                     */
+    int32_t *all_hi;      /* [n_candidates * (level-1)]                     */
+    int32_t *all_upper;   /* relaxed counts, -1 in a one-pass level         */
+    int32_t *all_exact;   /* exact counts, -1 where the relaxed pass pruned */
 } fe_level;
 
 typedef struct fe_result {
@@ -335,11 +374,14 @@ typedef struct fe_response {
     const int32_t *exact;   /* [M] host, -1 for pruned candidates             */
     int64_t arrival_ns, admit_ns, done_ns; /* steady clock (ns)               */
     int32_t round, round_size;             /* the round it ran in, its size   */
+    int64_t footprint;      /* device bytes the request needed in its round   */
 } fe_response;
 
 typedef struct fe_server_stats {
     int64_t submitted, completed, rejected, rounds;
     int32_t largest_round, max_inflight_seen;
+    int64_t budget_closed;  /* rounds closed because the next waiting request
+                               did not fit the round's share of hbm_budget   */
 } fe_server_stats;
 
 /* Create a server: the resident candidates (device table, fe_count layout)

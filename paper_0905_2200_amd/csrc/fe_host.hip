@@ -99,17 +99,21 @@ double now_ms()
 
 }  // namespace
 
+constexpr int NPARAM = 15;
+
 struct fe_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
-    int64_t param[10] = {0, 4096, 1024, 1, 0, 1, 548, 12651, 1, 0};
+    int64_t param[NPARAM] = {0, 4096, 1024, 1, 0, 1, -8136, 19504, 2, 0, 0, 9232, 5798, 800,
+                             131072};
     fe_stats stats{};
     // workspace
     Buf keys, hist, wmax, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
     Buf mtypes, mlen, mlo, mhi, mup, mex, msel, mn, mkey, tscr, tinfo, mfk, mfo, mfsel, pbc;
     Buf deep;  // window rings of the deep-class exact launches
+    Buf skey, sup;  // keys and relaxed counts of a level's elimination sample
     // This device's copy of the fixed scratch array (fe_count_noalloc), and
     // while such a call runs, the bump arena its workspace is carved from.
     char *fixed = nullptr;
@@ -313,16 +317,18 @@ struct StreamInfo {
 // PTPE, P = 1) once the tiles reach the crossover C(N) = a/N + b tiles,
 // else MapConcatenate with P >= 2 segments, enough for the target number of
 // waves, each segment long against the look-back (about n*W/span events).
-// a and b were fitted to measured crossovers on a 256-CU MI355X
-// (paper_0905_2200_amd/crossover.py), the paper's Table 1 and a/N + b fit.
-int choose_P(const fe_ctx *c, int tiles, const StreamInfo &si, int Wmax, int N)
+// a and b were fitted, per counter, to measured crossovers on a 256-CU
+// MI355X (paper_0905_2200_amd/crossover.py), as the paper fits its Table 1
+// with a/N + b.
+int choose_P(const fe_ctx *c, int tiles, const StreamInfo &si, int Wmax, int N, bool exact)
 {
     const int n = si.n;
     if (n <= 1) return 1;
     if (c->param[FE_PARAM_SEGMENTS] > 0)
         return (int)std::min<int64_t>(c->param[FE_PARAM_SEGMENTS], n);
-    const double cross = (double)c->param[FE_PARAM_CROSSOVER_A] / std::max(N, 1) +
-                         (double)c->param[FE_PARAM_CROSSOVER_B];
+    const int pa = exact ? FE_PARAM_CROSSOVER_A : FE_PARAM_CROSSOVER_A_RELAXED;
+    const int pb = exact ? FE_PARAM_CROSSOVER_B : FE_PARAM_CROSSOVER_B_RELAXED;
+    const double cross = (double)c->param[pa] / std::max(N, 1) + (double)c->param[pb];
     if ((double)tiles >= cross) return 1;
     const int64_t target = c->param[FE_PARAM_TARGET_WAVES];
     int64_t P = std::max<int64_t>(2, (target + tiles - 1) / std::max(tiles, 1));
@@ -394,7 +400,7 @@ struct Resume {
 // with rs, the incremental whole-stream Map instead.
 int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si,
                   const std::vector<GroupDesc> &groups, bool exact, int *out,
-                  const Resume *rs = nullptr)
+                  const Resume *rs = nullptr, const char *tag = "map")
 {
     hipStream_t s = c->stream;
     int rc;
@@ -451,7 +457,7 @@ int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo 
         g.lam = nullptr;
         g.tbl = nullptr;
         g.flags = nullptr;
-        g.P = rs ? 1 : choose_P(c, tiles, si, gd.wmax, N);
+        g.P = rs ? 1 : choose_P(c, tiles, si, gd.wmax, N, exact);
         if (c->arena) {
             // no-allocation call: as many segments as the fixed scratch's
             // remainder holds the tables of (P = 1 needs none)
@@ -477,7 +483,7 @@ int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo 
             continue;
         }
         char kname[40];
-        snprintf(kname, sizeof kname, "map_%s_n%d_d%d", exact ? "exact" : "relaxed", N,
+        snprintf(kname, sizeof kname, "%s_%s_n%d_d%d", tag, exact ? "exact" : "relaxed", N,
                  exact ? dcls_depth(dcls) : 1);
         const double ee = (double)gd.ncand * (double)si.n;
         c->stats.segments_max = std::max<int64_t>(c->stats.segments_max, g.P);
@@ -749,7 +755,7 @@ extern "C" int fe_destroy(fe_ctx *c)
                    &c->lam,  &c->tbl,  &c->flags, &c->sel, &c->nsel,  &c->status, &c->small, &c->cmask,
                    &c->mtypes, &c->mlen, &c->mlo, &c->mhi, &c->mup, &c->mex, &c->msel, &c->mn,
                    &c->mkey, &c->tscr, &c->tinfo, &c->mfk, &c->mfo, &c->mfsel, &c->pbc,
-                   &c->deep};
+                   &c->deep, &c->skey, &c->sup};
     for (Buf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto &p : c->pending) {
@@ -788,7 +794,10 @@ extern "C" int fe_sync(fe_ctx *c)
 extern "C" int fe_set_param(fe_ctx *c, int param, int64_t value)
 {
     if (!c) return FE_EINVAL;
-    if (param < 0 || param > 9 || value < 0) return fail(c, FE_EINVAL, "bad parameter");
+    const bool signed_ok = param == FE_PARAM_CROSSOVER_A || param == FE_PARAM_CROSSOVER_A_RELAXED;
+    if (param < 0 || param >= NPARAM || (value < 0 && !signed_ok))
+        return fail(c, FE_EINVAL, "bad parameter");
+    if (param == FE_PARAM_ELIMINATION && value > 2) return fail(c, FE_EINVAL, "bad parameter");
     if (param == FE_PARAM_TARGET_WAVES && value == 0) return fail(c, FE_EINVAL, "bad parameter");
     c->param[param] = value;
     return FE_OK;
@@ -796,7 +805,7 @@ extern "C" int fe_set_param(fe_ctx *c, int param, int64_t value)
 
 extern "C" int fe_get_param(const fe_ctx *c, int param, int64_t *value)
 {
-    if (!c || !value || param < 0 || param > 9) return FE_EINVAL;
+    if (!c || !value || param < 0 || param >= NPARAM) return FE_EINVAL;
     *value = c->param[param];
     return FE_OK;
 }
@@ -1159,7 +1168,29 @@ struct LevelOut {
     int64_t ncand, nsurv, nfreq;
     std::vector<int> types, lo, hi, upper, exact;
     double gen_ms, count_ms;
+    int passes = 2;
+    int64_t sample_n = 0, sample_kept = 0;
+    // every candidate (FE_PARAM_KEEP_CANDIDATES)
+    std::vector<int> all_types, all_lo, all_hi, all_upper, all_exact;
 };
+
+// keys (E1, lo1, hi1, E2, ...) of m-node episodes to types / lo / hi rows
+void split_keys(const int *key, size_t cnt, int m, std::vector<int> &ty, std::vector<int> &lo,
+                std::vector<int> &hi)
+{
+    ty.resize(cnt * m);
+    lo.resize(cnt * (m - 1));
+    hi.resize(cnt * (m - 1));
+    const int w = 3 * m - 2;
+    for (size_t i = 0; i < cnt; ++i) {
+        const int *k = key + i * w;
+        for (int j = 0; j < m; ++j) ty[i * m + j] = k[3 * j];
+        for (int j = 0; j < m - 1; ++j) {
+            lo[i * (m - 1) + j] = k[3 * j + 1];
+            hi[i * (m - 1) + j] = k[3 * j + 2];
+        }
+    }
+}
 
 // Host-side tiling of a level's candidates (all of size m) for the Map
 // kernels, in the packed tile layout the device grouping produces:
@@ -1435,6 +1466,37 @@ int dev_pack(fe_ctx *c, const int *key_d, int m, int64_t M, const int *up, int t
     return FE_OK;
 }
 
+// The elimination decision of a level (FE_PARAM_ELIMINATION = 2): the
+// relaxed pass over a sample of the level's candidates (every 64th block of
+// 64 consecutive ones, so join siblings stay together); ns sampled, nk of
+// them with upper >= theta.
+int sample_survival(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo &si, int level,
+                    int64_t M, int wbound, int bbound, int theta, int64_t &ns, int64_t &nk)
+{
+    int rc;
+    hipStream_t s = c->stream;
+    const int wk = 3 * level - 2;
+    ns = sample_count(M);
+    nk = 0;
+    if (ns <= 0) return FE_OK;
+    if ((rc = ensure(c, c->skey, (size_t)ns * wk * sizeof(int)))) return rc;
+    if ((rc = ensure(c, c->sup, (size_t)ns * sizeof(int)))) return rc;
+    launch_sample_keys(P<int>(c->mkey), wk, M, P<int>(c->skey), s);
+    std::vector<GroupDesc> groups;
+    int64_t kept = 0;
+    if ((rc = dev_pack(c, P<int>(c->skey), level, ns, nullptr, 0, false, wbound, bbound, groups,
+                       kept)))
+        return rc;
+    if ((rc = launch_groups(c, ids, ticks, si, groups, false, P<int>(c->sup), nullptr, "sample")))
+        return rc;
+    launch_fill(P<int>(c->mn), 0, 1, s);
+    launch_compact(P<int>(c->sup), (int)ns, theta, nullptr, P<int>(c->msel), P<int>(c->mn), s);
+    HIPCHK(c, hipMemcpyAsync(c->host, P<int>(c->mn), sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    nk = c->host[0];
+    return FE_OK;
+}
+
 }  // namespace
 
 extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int64_t n,
@@ -1485,6 +1547,12 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
                 L1.exact.push_back(hist[e]);
             }
         L1.nfreq = (int64_t)L1.types.size();
+        L1.passes = 1;
+        if (c->param[FE_PARAM_KEEP_CANDIDATES]) {
+            for (int e = 0; e < num_types; ++e) L1.all_types.push_back(e);
+            L1.all_upper = hist;
+            L1.all_exact = hist;
+        }
         L1.gen_ms = 0;
         L1.count_ms = now_ms() - t0;
         levels.push_back(std::move(L1));
@@ -1550,7 +1618,18 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         }
         HostPack hp;
         ivec order;
-        const bool elim = c->param[FE_PARAM_ELIMINATION] != 0;
+        const int64_t emode = c->param[FE_PARAM_ELIMINATION];
+        bool elim = emode != 0;
+        int64_t smp_n = 0, smp_kept = 0;
+        if (emode == 2 && !htile && (int64_t)M >= c->param[FE_PARAM_SAMPLE_MIN]) {
+            // two passes pay when the relaxed pass (cost r per candidate,
+            // relative to the exact one) prunes more than r of the level
+            if ((rc = sample_survival(c, ids, ticks, si, level, (int64_t)M, wbound, bbound, theta,
+                                      smp_n, smp_kept)))
+                return rc;
+            const double r = (double)c->param[FE_PARAM_PASS1_COST] / 1000.0;
+            elim = (double)smp_kept < (1.0 - r) * (double)smp_n;
+        }
         int64_t kept = 0;  // candidates of the exact pass (device tiling)
         if (!htile) {
             // prune and tile on the device: pass 1 (Algorithm 3) over every
@@ -1634,6 +1713,28 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
                                      s));
             HIPCHK(c, hipStreamSynchronize(s));
         }
+        LevelOut Lv;
+        Lv.passes = elim ? 2 : 1;
+        Lv.sample_n = smp_n;
+        Lv.sample_kept = smp_kept;
+        if (c->param[FE_PARAM_KEEP_CANDIDATES]) {
+            Lv.all_upper.resize(M);
+            Lv.all_exact.resize(M);
+            HIPCHK(c, hipMemcpyAsync(Lv.all_upper.data(), up, M * sizeof(int),
+                                     hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpyAsync(Lv.all_exact.data(), ex, M * sizeof(int),
+                                     hipMemcpyDeviceToHost, s));
+            std::vector<int> keys;
+            const int *kp = C.key.data();
+            if (djoin) {
+                keys.resize(M * wk);
+                HIPCHK(c, hipMemcpyAsync(keys.data(), P<int>(c->mkey), M * wk * sizeof(int),
+                                         hipMemcpyDeviceToHost, s));
+                kp = keys.data();
+            }
+            HIPCHK(c, hipStreamSynchronize(s));
+            split_keys(kp, M, level, Lv.all_types, Lv.all_lo, Lv.all_hi);
+        }
         Episodes NF;
         NF.m = level;
         NF.key.resize((size_t)nf * wk);
@@ -1651,7 +1752,6 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
                 std::memcpy(NF.key.data() + (size_t)i * wk, C.at(fsel[i]), wk * sizeof(int));
         }
         sort_episodes(NF, &fup, &fex);
-        LevelOut Lv;
         Lv.level = level;
         Lv.ncand = (int64_t)M;
         Lv.nsurv = cnts[1];
@@ -1707,6 +1807,16 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         d.exact = dup(L.exact);
         d.gen_ms = L.gen_ms;
         d.count_ms = L.count_ms;
+        d.passes = L.passes;
+        d.sample_n = L.sample_n;
+        d.sample_kept = L.sample_kept;
+        auto dup_opt = [&](const std::vector<int> &v, bool on) { return on ? dup(v) : nullptr; };
+        const bool all = !L.all_exact.empty() || (L.ncand == 0 && c->param[FE_PARAM_KEEP_CANDIDATES]);
+        d.all_types = dup_opt(L.all_types, all);
+        d.all_lo = dup_opt(L.all_lo, all);
+        d.all_hi = dup_opt(L.all_hi, all);
+        d.all_upper = dup_opt(L.all_upper, all);
+        d.all_exact = dup_opt(L.all_exact, all);
     }
     *out = r;
     c->stats.last_call_ms = now_ms() - t_call;
@@ -1722,6 +1832,11 @@ extern "C" void fe_result_free(fe_result *r)
         std::free(r->levels[i].hi);
         std::free(r->levels[i].upper);
         std::free(r->levels[i].exact);
+        std::free(r->levels[i].all_types);
+        std::free(r->levels[i].all_lo);
+        std::free(r->levels[i].all_hi);
+        std::free(r->levels[i].all_upper);
+        std::free(r->levels[i].all_exact);
     }
     std::free(r->levels);
     std::free(r);
@@ -2329,19 +2444,31 @@ int server_launch(fe_server *sv, fe_server::Lane &ln)
         if (tl.empty()) continue;
         LvPlan L{};
         L.N = N;
+        // work items heaviest first (cost n/P); the tiles of one request and
+        // group share their cost, so runs of equal-cost tiles are ordered,
+        // not the items one by one
         auto add_items = [&](const std::vector<int> &ts, int64_t &off, int64_t &cnt) {
-            std::vector<std::pair<int64_t, int2>> v;
-            for (int t : ts) {
-                const int Pn = td[t].P;
-                const int64_t cost = (int64_t)bj[td[t].job].n / Pn + 1;
-                for (int p = 0; p < Pn; ++p) v.push_back({cost, make_int2(t, p)});
+            std::vector<std::pair<int64_t, size_t>> runs;  // (cost, first position in ts)
+            for (size_t i = 0; i < ts.size(); ++i) {
+                const int t = ts[i];
+                const int64_t cost = (int64_t)bj[td[t].job].n / td[t].P + 1;
+                if (i == 0 || td[t].job != td[ts[i - 1]].job || cost != runs.back().first)
+                    runs.push_back({cost, i});
             }
-            std::stable_sort(v.begin(), v.end(),
-                             [](const std::pair<int64_t, int2> &a,
-                                const std::pair<int64_t, int2> &b2) { return a.first > b2.first; });
+            std::stable_sort(runs.begin(), runs.end(),
+                             [](const std::pair<int64_t, size_t> &a,
+                                const std::pair<int64_t, size_t> &b2) { return a.first > b2.first; });
             off = (int64_t)items.size();
-            cnt = (int64_t)v.size();
-            for (auto &e : v) items.push_back(e.second);
+            for (size_t k = 0; k < runs.size(); ++k) {
+                const size_t i0 = runs[k].second;
+                size_t i1 = i0 + 1;
+                while (i1 < ts.size() && td[ts[i1]].job == td[ts[i0]].job &&
+                       (int64_t)bj[td[ts[i1]].job].n / td[ts[i1]].P + 1 == runs[k].first)
+                    ++i1;
+                for (size_t i = i0; i < i1; ++i)
+                    for (int p = 0; p < td[ts[i]].P; ++p) items.push_back(make_int2(ts[i], p));
+            }
+            cnt = (int64_t)items.size() - off;
         };
         add_items(tl, L.it_rel, L.n_rel);
         for (int d = 0; d < NDCLS; ++d) {
@@ -2539,7 +2666,10 @@ void server_loop(fe_server *sv)
             const int64_t now = steady_ns();
             while (!sv->pending.empty() && (int)free_lane->reqs.size() < sv->cfg.max_round) {
                 fe_server::Req *q = sv->pending.front();
-                if (!free_lane->reqs.empty() && used + q->foot > lane_budget) break;
+                if (!free_lane->reqs.empty() && used + q->foot > lane_budget) {
+                    sv->st.budget_closed++;
+                    break;
+                }
                 sv->pending.pop_front();
                 used += q->foot;
                 q->state = 1;
@@ -2792,6 +2922,7 @@ void fill_response(const fe_server::Req *q, fe_response *out)
     out->done_ns = q->done;
     out->round = q->round;
     out->round_size = q->rsize;
+    out->footprint = q->foot;
 }
 }  // namespace
 

@@ -155,6 +155,11 @@ void launch_tile_lanes(int64_t M, const int *scratch, const int *info, int *orig
 void launch_join(const int *F, int w, const int64_t *first, const int64_t *off, int64_t cnt,
                  int64_t M, int *out, hipStream_t s);
 void launch_gather_keys(const int *key, int w, const int *sel, int nsel, int *out, hipStream_t s);
+// Sample of a level for the elimination decision: every SAMPLE_STRIDE-th
+// block of 64 consecutive candidates; sample_count(M) candidates.
+constexpr int SAMPLE_STRIDE = 64;
+int64_t sample_count(int64_t M);
+void launch_sample_keys(const int *key, int w, int64_t M, int *out, hipStream_t s);
 // Exclusive scan of n ints (scratch: scan_scratch_ints(n) ints; its first
 // holds the total).
 int64_t scan_scratch_ints(int64_t n);

@@ -389,7 +389,34 @@ __global__ void k_gather_keys(const int *__restrict__ key, int w, const int *__r
     const int k = (int)(t - i * w);
     out[t] = key[(int64_t)sel[i] * w + k];
 }
+// Keys of a sample of the level: every SAMPLE_STRIDE-th block of WAVE
+// consecutive candidates (whole blocks keep runs of join siblings together).
+__global__ void k_sample_keys(const int *__restrict__ key, int w, int64_t ns,
+                              int *__restrict__ out)
+{
+    const int64_t t = blockIdx.x * (int64_t)TB + threadIdx.x;
+    if (t >= ns * w) return;
+    const int64_t i = t / w;
+    const int k = (int)(t - i * w);
+    const int64_t j = i / WAVE * WAVE * SAMPLE_STRIDE + i % WAVE;
+    out[t] = key[j * w + k];
+}
 }  // namespace
+
+int64_t sample_count(int64_t M)
+{
+    const int64_t span = (int64_t)WAVE * SAMPLE_STRIDE;
+    const int64_t r = M % span;
+    return M / span * WAVE + (r < WAVE ? r : WAVE);
+}
+
+void launch_sample_keys(const int *key, int w, int64_t M, int *out, hipStream_t s)
+{
+    const int64_t n = sample_count(M) * w;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_sample_keys, dim3((unsigned)((n + TB - 1) / TB)), dim3(TB), 0, s, key, w,
+                       sample_count(M), out);
+}
 
 int64_t scan_scratch_ints(int64_t n) { return (n + CHUNK - 1) / CHUNK + 1; }
 

@@ -19,7 +19,8 @@ FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_EUNSORTED, FE_ERANGE, FE_EBUSY, FE_E
 FE_EXACT, FE_RELAXED = 0, 1
 PARAM_SEGMENTS, PARAM_TARGET_WAVES, PARAM_MIN_SEG_EVENTS, PARAM_CONCAT_TREE, PARAM_TIMING, \
     PARAM_TYPE_DISPATCH, PARAM_CROSSOVER_A, PARAM_CROSSOVER_B, PARAM_ELIMINATION, \
-    PARAM_HOST_TILING = range(10)
+    PARAM_HOST_TILING, PARAM_KEEP_CANDIDATES, PARAM_CROSSOVER_A_RELAXED, \
+    PARAM_CROSSOVER_B_RELAXED, PARAM_PASS1_COST, PARAM_SAMPLE_MIN = range(15)
 
 STATUS_NAMES = {0: "FE_OK", 1: "FE_EINVAL", 2: "FE_ENOMEM", 3: "FE_EDEVICE",
                 4: "FE_EUNSORTED", 5: "FE_ERANGE", 6: "FE_EBUSY", 7: "FE_EINTERNAL"}
@@ -47,7 +48,13 @@ class _Level(ctypes.Structure):
                 ("types", ctypes.POINTER(ctypes.c_int32)), ("lo", ctypes.POINTER(ctypes.c_int32)),
                 ("hi", ctypes.POINTER(ctypes.c_int32)), ("upper", ctypes.POINTER(ctypes.c_int32)),
                 ("exact", ctypes.POINTER(ctypes.c_int32)), ("gen_ms", ctypes.c_double),
-                ("count_ms", ctypes.c_double)]
+                ("count_ms", ctypes.c_double), ("passes", ctypes.c_int32),
+                ("sample_n", ctypes.c_int64), ("sample_kept", ctypes.c_int64),
+                ("all_types", ctypes.POINTER(ctypes.c_int32)),
+                ("all_lo", ctypes.POINTER(ctypes.c_int32)),
+                ("all_hi", ctypes.POINTER(ctypes.c_int32)),
+                ("all_upper", ctypes.POINTER(ctypes.c_int32)),
+                ("all_exact", ctypes.POINTER(ctypes.c_int32))]
 
 
 class _Result(ctypes.Structure):
@@ -95,13 +102,14 @@ class _Response(ctypes.Structure):
                 ("upper", ctypes.POINTER(ctypes.c_int32)), ("exact", ctypes.POINTER(ctypes.c_int32)),
                 ("arrival_ns", ctypes.c_int64), ("admit_ns", ctypes.c_int64),
                 ("done_ns", ctypes.c_int64), ("round", ctypes.c_int32),
-                ("round_size", ctypes.c_int32)]
+                ("round_size", ctypes.c_int32), ("footprint", ctypes.c_int64)]
 
 
 class _ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("rejected", ctypes.c_int64), ("rounds", ctypes.c_int64),
-                ("largest_round", ctypes.c_int32), ("max_inflight_seen", ctypes.c_int32)]
+                ("largest_round", ctypes.c_int32), ("max_inflight_seen", ctypes.c_int32),
+                ("budget_closed", ctypes.c_int64)]
 
 
 _lib = None
@@ -367,14 +375,24 @@ class Context:
                         return np.zeros(0, np.int32)
                     return np.ctypeslib.as_array(p, shape=(cnt,)).copy()
 
-                out.append({
+                d = {
                     "level": lev, "n_candidates": int(L.n_candidates),
                     "n_survivors": int(L.n_survivors), "n_frequent": F,
                     "types": arr(L.types, F * lev).reshape(F, lev),
                     "lo": arr(L.lo, F * (lev - 1)).reshape(F, lev - 1),
                     "hi": arr(L.hi, F * (lev - 1)).reshape(F, lev - 1),
                     "upper": arr(L.upper, F), "exact": arr(L.exact, F),
-                    "gen_ms": float(L.gen_ms), "count_ms": float(L.count_ms)})
+                    "gen_ms": float(L.gen_ms), "count_ms": float(L.count_ms),
+                    "passes": int(L.passes), "sample_n": int(L.sample_n),
+                    "sample_kept": int(L.sample_kept)}
+                if L.all_exact:
+                    Mc = int(L.n_candidates)
+                    d.update({"all_types": arr(L.all_types, Mc * lev).reshape(Mc, lev),
+                              "all_lo": arr(L.all_lo, Mc * (lev - 1)).reshape(Mc, lev - 1),
+                              "all_hi": arr(L.all_hi, Mc * (lev - 1)).reshape(Mc, lev - 1),
+                              "all_upper": arr(L.all_upper, Mc),
+                              "all_exact": arr(L.all_exact, Mc)})
+                out.append(d)
         finally:
             lib().fe_result_free(res)
         return out

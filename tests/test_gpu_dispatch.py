@@ -168,64 +168,99 @@ def test_mining_same_with_and_without_dispatch(ctx, fe):
 
 def test_hybrid_crossover_rule(ctx, fe):
     # below the crossover C(N) = A/N + B tiles the count is segmented (P >= 2),
-    # at or above it whole-stream (P = 1); the counts are the same
+    # at or above it whole-stream (P = 1); each counter has its own A and B;
+    # the counts are the same
     rng = np.random.default_rng(41)
     ids_h, ticks_h = _stream(rng, 50_000, 16)
     # 40 tiles in one group (one list-depth class)
     cand = _prefix_runs(rng, 4, 40, [(1, 2, 3), (4, 5, 6)], np.arange(16),
                         ivs=[(50, 100), (100, 200)])
     ids, ticks = ctx.stream_tensors(ids_h, ticks_h)
-    A0, B0 = ctx.get_param(fe.PARAM_CROSSOVER_A), ctx.get_param(fe.PARAM_CROSSOVER_B)
-    assert A0 / 4 + B0 > 40
-    want = oracle_counts(ids_h, ticks_h, 16, cand, EXACT)
+    keys = (fe.PARAM_CROSSOVER_A, fe.PARAM_CROSSOVER_B, fe.PARAM_CROSSOVER_A_RELAXED,
+            fe.PARAM_CROSSOVER_B_RELAXED)
+    saved = {p: ctx.get_param(p) for p in keys}
+    A0, B0, AR, BR = (saved[p] for p in keys)
+    assert A0 / 4 + B0 > 40 and AR / 4 + BR > 40
+    want = {m: oracle_counts(ids_h, ticks_h, 16, cand, m) for m in (EXACT, RELAXED)}
+
+    def run(mode):
+        got = ctx.count(ids, ticks, 16, cand, mode).cpu().numpy()
+        assert (got == want[mode]).all()
+        return ctx.stats()["segments_max"]
     try:
-        got = ctx.count(ids, ticks, 16, cand, EXACT).cpu().numpy()
-        assert ctx.stats()["segments_max"] >= 2
-        assert (got == want).all()
+        assert run(EXACT) >= 2 and run(RELAXED) >= 2
         ctx.set_param(fe.PARAM_CROSSOVER_A, 0)
         ctx.set_param(fe.PARAM_CROSSOVER_B, 40)   # C(4) = 40 tiles: whole stream
-        got = ctx.count(ids, ticks, 16, cand, EXACT).cpu().numpy()
-        assert ctx.stats()["segments_max"] == 1
-        assert (got == want).all()
+        assert run(EXACT) == 1
+        assert run(RELAXED) >= 2                  # the relaxed rule is its own
         ctx.set_param(fe.PARAM_CROSSOVER_B, 41)
-        ctx.count(ids, ticks, 16, cand, EXACT)
-        assert ctx.stats()["segments_max"] >= 2
+        assert run(EXACT) >= 2
+        ctx.set_param(fe.PARAM_CROSSOVER_A_RELAXED, -40)
+        ctx.set_param(fe.PARAM_CROSSOVER_B_RELAXED, 50)   # C(4) = 40
+        assert run(RELAXED) == 1
+        ctx.set_param(fe.PARAM_CROSSOVER_B_RELAXED, 51)
+        assert run(RELAXED) >= 2
+        with pytest.raises(fe.FeError):
+            ctx.set_param(fe.PARAM_CROSSOVER_B, -1)   # only A may be negative
     finally:
-        ctx.set_param(fe.PARAM_CROSSOVER_A, A0)
-        ctx.set_param(fe.PARAM_CROSSOVER_B, B0)
+        for p, v in saved.items():
+            ctx.set_param(p, v)
 
 
 def test_one_pass_mining_same_result(ctx, fe):
-    # Algorithm 1 over every candidate (no elimination) finds the same frequent
-    # episodes with the same exact counts as the two-pass form
+    # Algorithm 1 over every candidate (no elimination), two passes at every
+    # level, and the per-level decision from a sampled relaxed pass find the
+    # same frequent episodes with the same exact counts
     s = synth.config_mining(duration_s=60.0)
     ids, ticks = ctx.stream_tensors(s["ids"], s["ticks"])
+    saved = {p: ctx.get_param(p) for p in (fe.PARAM_ELIMINATION, fe.PARAM_SAMPLE_MIN,
+                                            fe.PARAM_PASS1_COST)}
     res = {}
-    for elim in (1, 0):
-        ctx.set_param(fe.PARAM_ELIMINATION, elim)
-        try:
-            res[elim] = ctx.mine(ids, ticks, s["num_types"], s["intervals"], s["theta"], 5)
-        finally:
-            ctx.set_param(fe.PARAM_ELIMINATION, 1)
-    assert len(res[0]) == len(res[1])
-    for a, b in zip(res[1], res[0]):
-        for k in ("types", "lo", "hi", "exact"):
-            assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (a["level"], k)
-        if a["level"] >= 2:
-            assert (np.asarray(b["upper"]) == -1).all()
-            assert b["n_survivors"] == b["n_candidates"]
+    try:
+        ctx.set_param(fe.PARAM_SAMPLE_MIN, 1000)
+        for key, elim, cost in (("two", 1, 800), ("one", 0, 800), ("rule_two", 2, 0),
+                                ("rule_one", 2, 1000), ("rule", 2, 800)):
+            ctx.set_param(fe.PARAM_ELIMINATION, elim)
+            ctx.set_param(fe.PARAM_PASS1_COST, cost)
+            res[key] = ctx.mine(ids, ticks, s["num_types"], s["intervals"], s["theta"], 5)
+    finally:
+        for p, v in saved.items():
+            ctx.set_param(p, v)
+    for key in res:
+        assert [L["level"] for L in res[key]] == [L["level"] for L in res["two"]], key
+        for a, b in zip(res["two"], res[key]):
+            for k in ("types", "lo", "hi", "exact", "n_frequent", "n_candidates"):
+                assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (key, a["level"], k)
+            if a["level"] < 2:
+                continue
+            if b["passes"] == 1:
+                assert (np.asarray(b["upper"]) == -1).all()
+                assert b["n_survivors"] == b["n_candidates"]
+            else:
+                assert np.array_equal(a["upper"], b["upper"]) and \
+                    a["n_survivors"] == b["n_survivors"], (key, a["level"])
+    big = [L for L in res["rule"] if L["level"] >= 2 and L["n_candidates"] >= 1000]
+    assert big and all(L["sample_n"] > 0 for L in big)
+    for L in res["rule"]:
+        if L["sample_n"]:
+            want = 2 if L["sample_kept"] < 0.2 * L["sample_n"] else 1
+            assert L["passes"] == want, L["level"]
+    assert all(L["passes"] == 2 for L in res["rule_two"] if L["level"] >= 2)
+    assert all(L["passes"] == 1 for L in res["rule_one"] if L["sample_n"])
+    assert all(L["passes"] == 1 for L in res["one"] if L["level"] >= 2)
 
 
 def _mine_with(ctx, fe, s, intervals, theta, max_level, htile, elim):
     ids, ticks = ctx.stream_tensors(s["ids"], s["ticks"])
     h0 = ctx.get_param(fe.PARAM_HOST_TILING)
+    e0 = ctx.get_param(fe.PARAM_ELIMINATION)
     ctx.set_param(fe.PARAM_HOST_TILING, htile)
     ctx.set_param(fe.PARAM_ELIMINATION, elim)
     try:
         return ctx.mine(ids, ticks, s["num_types"], intervals, theta, max_level)
     finally:
         ctx.set_param(fe.PARAM_HOST_TILING, h0)
-        ctx.set_param(fe.PARAM_ELIMINATION, 1)
+        ctx.set_param(fe.PARAM_ELIMINATION, e0)
 
 
 def _same_levels(a, b):

@@ -202,8 +202,10 @@ def test_mining_matches_oracle_small(ctx):
         L = lv["level"]
         w = want[L]
         assert lv["n_candidates"] == len(w["candidates"]), L
-        if L > 1:
+        if L > 1 and lv["passes"] == 2:
             assert lv["n_survivors"] == int((w["upper"] >= s["theta"]).sum()), L
+        elif L > 1:
+            assert lv["n_survivors"] == lv["n_candidates"], L
         g = {(tuple(t), tuple(a), tuple(b)): (int(u), int(x))
              for t, a, b, u, x in zip(lv["types"], lv["lo"], lv["hi"], lv["upper"], lv["exact"])}
         wf = {}

@@ -68,3 +68,71 @@ def test_mining_planted_cascade_found_and_anti_monotone():
             assert x <= prev[(ty[:-1], lo[:-1], hi[:-1])] and x <= prev[(ty[1:], lo[1:], hi[1:])]
         up, ex = res[level]["upper"], res[level]["exact"]
         assert ((ex == -1) | (up >= ex)).all()
+
+
+def _as_tuples(t, a, b):
+    return [(tuple(x), tuple(y), tuple(z)) for x, y, z in zip(t.tolist(), a.tolist(), b.tolist())]
+
+
+def test_array_generation_equals_tuple_generation():
+    """The array form of the candidate generation (used for the full-size
+    golden values) yields the tuple form's candidates in the same order."""
+    rng = np.random.default_rng(3)
+    F1 = [0, 2, 5]
+    I = [(0, 3), (2, 6), (1, 9)]
+    assert _as_tuples(*mine.gen_level2_arrays(F1, I)) == mine.gen_level2(F1, I)
+    checked = 0
+    for trial in range(300):
+        T = int(rng.integers(2, 5))
+        Iv = I[:int(rng.integers(1, 4))]
+        l = int(rng.integers(1, 5))
+        eps = set()
+        for _ in range(int(rng.integers(1, 60))):
+            ty = tuple(int(x) for x in rng.integers(0, T, l))
+            iv = [Iv[int(rng.integers(len(Iv)))] for _ in range(l - 1)]
+            eps.add((ty, tuple(a for a, _ in iv), tuple(b for _, b in iv)))
+        F = sorted(eps)
+        t = np.array([e[0] for e in F], np.int32).reshape(len(F), l)
+        a = np.array([e[1] for e in F], np.int32).reshape(len(F), l - 1)
+        b = np.array([e[2] for e in F], np.int32).reshape(len(F), l - 1)
+        assert _as_tuples(*mine.sort_episodes(t[::-1].copy(), a[::-1].copy(),
+                                              b[::-1].copy())) == F
+        got = _as_tuples(*mine.gen_next_arrays(t, a, b))
+        assert got == mine.gen_next(F), trial
+        checked += len(got)
+    assert checked > 1000
+
+
+def test_array_miner_equals_tuple_miner():
+    for tr in range(2):
+        s = synth.config_mining(n_neurons=10, rate_hz=15.0, duration_s=60.0, n_cascades=2,
+                                tag=60 + tr)
+        a = mine.mine_arrays(s["ids"], s["ticks"], s["num_types"], s["intervals"], s["theta"], 6,
+                             keep=lambda L, M: True if L % 2 == 0 else np.arange(0, M, 7),
+                             planted=lambda L: np.zeros((0, 3 * L - 2), np.int64))
+        b = mine.mine(s["ids"], s["ticks"], s["num_types"], s["intervals"], s["theta"], 6)
+        assert sorted(a) == sorted(b)
+        for L in b:
+            got = {e: (int(u), int(x)) for e, u, x in
+                   zip(_as_tuples(a[L]["types"], a[L]["lo"], a[L]["hi"]), a[L]["upper"],
+                       a[L]["exact"])}
+            want = {e: (int(b[L]["upper"][k]), int(b[L]["exact"][k]))
+                    for k, e in enumerate(b[L]["candidates"]) if e in b[L]["frequent"]}
+            assert got == want, (tr, L)
+            assert a[L]["n_candidates"] == len(b[L]["candidates"])
+            if L > 1:
+                assert a[L]["n_survivors"] == int((b[L]["upper"] >= s["theta"]).sum())
+            if "all_types" in a[L]:
+                assert _as_tuples(a[L]["all_types"], a[L]["all_lo"], a[L]["all_hi"]) == \
+                    b[L]["candidates"]
+                assert (a[L]["all_upper"] == b[L]["upper"]).all()
+                kept = b[L]["exact"] >= 0
+                assert (a[L]["all_exact"][kept] == b[L]["exact"][kept]).all()
+                assert (a[L]["all_exact"] <= a[L]["all_upper"]).all()
+            if "sample_idx" in a[L]:
+                idx = a[L]["sample_idx"]
+                assert _as_tuples(a[L]["sample_types"], a[L]["sample_lo"], a[L]["sample_hi"]) == \
+                    [b[L]["candidates"][i] for i in idx]
+                assert (a[L]["sample_upper"] == b[L]["upper"][idx]).all()
+                kept = b[L]["exact"][idx] >= 0
+                assert (a[L]["sample_exact"][kept] == b[L]["exact"][idx][kept]).all()
