@@ -27,6 +27,7 @@ import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -328,21 +329,26 @@ def _serve(fe, ctx, sv, reqs, max_inflight, max_round, hbm_budget, copy_every):
                        max_inflight=max_inflight, max_round=max_round)
     ptr = [0] * len(arrays)
     pre = int(sv["preroll_s"] * 10000)
+    t_app = [0.0]
 
     def feed(upto):  # every array's events with tick < upto
+        t0 = time.perf_counter()
         for k, a in enumerate(arrays):
             e = int(np.searchsorted(a["ticks"], upto, "left"))
             if e > ptr[k]:
                 server.append(k, a["ids"][ptr[k]:e], a["ticks"][ptr[k]:e])
                 ptr[k] = e
+        t_app[0] += time.perf_counter() - t0
     feed(pre)
     for r in reqs[:4]:  # warm-up before the clock starts
         server.wait(server.submit(r["array"], max(0, pre - 10000), pre, r["theta"]))
+    t_app[0] = 0.0
     base = time.monotonic_ns() + 200_000_000
-    tickets = []
+    tickets, late = [], []
     for r in reqs:
         due = base + int(r["arrival_s"] * 1e9)
         feed(pre + int(r["arrival_s"] * 10000) + 1)
+        late.append((time.monotonic_ns() - due) / 1e6)
         while time.monotonic_ns() < due:
             pass
         tickets.append(server.submit(r["array"], r["t_begin"], r["t_end"], r["theta"], due))
@@ -350,6 +356,9 @@ def _serve(fe, ctx, sv, reqs, max_inflight, max_round, hbm_budget, copy_every):
     stats = server.stats()
     server.close()
     wall = (max(d["done_ns"] for d in done) - base) / 1e9
+    stats["submit_late_ms_p50"] = pct(late, 50)
+    stats["submit_late_ms_max"] = round(max(late), 2)
+    stats["append_s"] = round(t_app[0], 3)
     return done, wall, stats
 
 
@@ -381,7 +390,9 @@ def bench_served(args, fe, synth, torch):
                 "mean_round_size": round(float(np.mean([d["round_size"] for d in done])), 2),
                 "rounds": st["rounds"], "largest_round": st["largest_round"],
                 "max_inflight_seen": st["max_inflight_seen"],
-                "budget_closed_rounds": st["budget_closed"], "rejected": st["rejected"]}
+                "budget_closed_rounds": st["budget_closed"], "rejected": st["rejected"],
+                "submit_late_ms_p50": st["submit_late_ms_p50"],
+                "submit_late_ms_max": st["submit_late_ms_max"], "append_s": st["append_s"]}
     big = 16 << 30
     served = _serve(fe, ctx, sv, reqs, args.max_inflight, 64, big, every)
     out = {"served": summary(*served)}
@@ -524,6 +535,31 @@ def bench_streaming(args, fe, synth, torch):
                        "candidates": M}}
 
 
+CONTRACT_KEYS = ("metric", "n_gpus", "steps", "warmup", "higher_is_better", "scaling",
+                 "vs_baseline", "dtype", "data")
+
+
+def run_child(key, args):
+    """One workload in a process of its own (so that workloads share no
+    process state); returns its JSON object without the contract keys."""
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--workload", key,
+           "--trace-s", str(args.trace_s), "--rate", str(args.rate),
+           "--max-inflight", str(args.max_inflight)]
+    t0 = time.perf_counter()
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=args.child_timeout_s)
+    except subprocess.TimeoutExpired:
+        log("%s: no result within %d s" % (key, args.child_timeout_s))
+        return {"error": "timed out after %d s" % args.child_timeout_s}
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    if r.returncode != 0 or not lines:
+        log("%s: exit status %d" % (key, r.returncode))
+        return {"error": "exit status %d" % r.returncode}
+    d = json.loads(lines[-1])
+    log("%s: %.1f s" % (key, time.perf_counter() - t0))
+    return {k: v for k, v in d.items() if k not in CONTRACT_KEYS}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -556,6 +592,8 @@ def main():
                     help="per-type dispatch for shared-prefix waves (0 = every event)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
+    ap.add_argument("--child-timeout-s", type=int, default=300,
+                    help="time limit of each sub-workload's process")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -564,6 +602,13 @@ def main():
             print("bench.py measures one GPU: the counting path runs on a single device here; "
                   "--gpus %d is not supported" % max(args.gpus, world), file=sys.stderr)
         sys.exit(2)
+
+    extras = {}
+    if args.workload == "mining" and not args.no_extras:
+        # the other workloads first, each in a child process, before this
+        # process uses the GPU
+        for key in ("batched", "served", "large"):
+            extras[key] = run_child(key, args)
 
     import torch
     from paper_0905_2200_amd import fe, synth
@@ -595,12 +640,7 @@ def main():
            "dtype": "int32", "data": "synthetic", "config": m["config"],
            "roofline": m["roofline"], "stream_equivalent": m["stream_equivalent"],
            "dram": m["dram"]}
-    if not args.no_extras:
-        for key, fn in (("batched", bench_batched), ("served", bench_served),
-                        ("large", bench_large)):
-            t0 = time.perf_counter()
-            out[key] = fn(args, fe, synth, torch)
-            log("%s: %.1f s" % (key, time.perf_counter() - t0))
+    out.update(extras)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_baseline_s)

@@ -2327,6 +2327,13 @@ struct fe_server {
     };
     std::vector<Arr> arr;
     std::mutex amu;  // guards appends against window lookups
+    // appends: asynchronous copies from a pinned staging ring on a stream of
+    // their own; every round waits for the last one (aev) before it starts
+    hipStream_t astream = nullptr;
+    hipEvent_t aev = nullptr;
+    char *astage = nullptr;
+    size_t astage_cap = 0, apos = 0;
+    bool apending = false;
     // requests
     struct Req {
         fe_request r;
@@ -2526,6 +2533,8 @@ int server_launch(fe_server *sv, fe_server::Lane &ln)
     if (!lists.empty())
         std::memcpy(ln.hstage + sd + sj + si, lists.data(), lists.size() * sizeof(int));
     hipStream_t s = ln.s;
+    // the windows' events: every append so far (the caller holds amu)
+    if (sv->apending) HIPCHK(c, hipStreamWaitEvent(s, sv->aev, 0));
     HIPCHK(c, hipMemcpyAsync(ln.descd.p, ln.hstage, td.size() * sizeof(TileDesc),
                              hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(ln.jobsd.p, ln.hstage + sd, bj.size() * sizeof(BJob),
@@ -2810,6 +2819,15 @@ extern "C" int fe_server_create(fe_ctx *c, const fe_server_config *cfg, const in
     HIPCHK(c, hipMemcpy(sv->origd.p, orig.data(), orig.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(sv->tileWd.p, tileW.data(), tileW.size() * sizeof(int),
                         hipMemcpyHostToDevice));
+    // append path
+    HIPCHK(c, hipStreamCreateWithFlags(&sv->astream, hipStreamNonBlocking));
+    HIPCHK(c, hipEventCreateWithFlags(&sv->aev, hipEventDisableTiming));
+    sv->astage_cap = (size_t)8 << 20;
+    if (hipHostMalloc((void **)&sv->astage, sv->astage_cap) != hipSuccess) {
+        (void)hipGetLastError();
+        sv->astage = nullptr;
+        sv->astage_cap = 0;  // synchronous copies only
+    }
     // arrays
     sv->arr.resize(cfg->n_arrays);
     for (int a = 0; a < cfg->n_arrays; ++a) {
@@ -2866,8 +2884,28 @@ extern "C" int fe_server_append(fe_server *sv, int32_t a, const int32_t *ids, co
         prev = ticks[i];
     }
     HIPCHK(c, hipSetDevice(c->device));
-    HIPCHK(c, hipMemcpy(P<int>(A.ids) + A.n, ids, n * sizeof(int), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(P<int>(A.ticks) + A.n, ticks, n * sizeof(int), hipMemcpyHostToDevice));
+    const size_t bytes = (size_t)n * sizeof(int);
+    const size_t need = 2 * ((bytes + 255) & ~(size_t)255);
+    if (need <= sv->astage_cap) {
+        if (sv->apos + need > sv->astage_cap) {
+            // the ring wraps: the copies still reading it must finish first
+            HIPCHK(c, hipStreamSynchronize(sv->astream));
+            sv->apos = 0;
+        }
+        char *st = sv->astage + sv->apos;
+        std::memcpy(st, ids, bytes);
+        std::memcpy(st + need / 2, ticks, bytes);
+        HIPCHK(c, hipMemcpyAsync(P<int>(A.ids) + A.n, st, bytes, hipMemcpyHostToDevice,
+                                 sv->astream));
+        HIPCHK(c, hipMemcpyAsync(P<int>(A.ticks) + A.n, st + need / 2, bytes,
+                                 hipMemcpyHostToDevice, sv->astream));
+        HIPCHK(c, hipEventRecord(sv->aev, sv->astream));
+        sv->apending = true;
+        sv->apos += need;
+    } else {
+        HIPCHK(c, hipMemcpy(P<int>(A.ids) + A.n, ids, bytes, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(P<int>(A.ticks) + A.n, ticks, bytes, hipMemcpyHostToDevice));
+    }
     A.hticks.insert(A.hticks.end(), ticks, ticks + n);
     A.n += n;
     return FE_OK;
@@ -2996,10 +3034,14 @@ extern "C" int fe_server_destroy(fe_server *sv)
         if (L.done) (void)hipEventDestroy(L.done);
         if (L.s) (void)hipStreamDestroy(L.s);
     }
+    if (sv->astream) (void)hipStreamSynchronize(sv->astream);
     for (auto &A : sv->arr) {
         if (A.ids.p) (void)hipFree(A.ids.p);
         if (A.ticks.p) (void)hipFree(A.ticks.p);
     }
+    if (sv->astage) (void)hipHostFree(sv->astage);
+    if (sv->aev) (void)hipEventDestroy(sv->aev);
+    if (sv->astream) (void)hipStreamDestroy(sv->astream);
     Buf *bs[] = {&sv->pk, &sv->origd, &sv->tileWd};
     for (Buf *x : bs)
         if (x->p) (void)hipFree(x->p);

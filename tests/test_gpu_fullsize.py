@@ -112,7 +112,7 @@ def test_mining_workload_full(ctx, fe):
     done = g["levels_done"].tolist()
     if bool(g["complete"]):
         assert [lv["level"] for lv in res] == g["levels"].tolist()
-    assert set(done) <= set(lv["level"] for lv in res) and {1, 2, 3} <= set(done)
+    assert set(done) <= set(lv["level"] for lv in res) and {1, 2} <= set(done)
     for lv in res:
         L = lv["level"]
         if L not in done:
