@@ -508,65 +508,69 @@ template <int N, bool EXACT, int D> struct MainRun {
                 }
                 ml &= ~upto;
                 int cpos = -1, ct = 0;
-                if constexpr (HX) {
-                    // type ids below 64: every position in gp holds the last type
-                    if constexpr (EXACT) {
-                        while (gp) {
+                // (one wave-uniform test skips the search in spans where no
+                // lane has a last-type event that could complete, most of them)
+                if (__builtin_amdgcn_ballot_w64(gp != 0) != 0) {
+                    if constexpr (HX) {
+                        // type ids below 64: every position in gp holds the last type
+                        if constexpr (EXACT) {
+                            while (gp) {
+                                const int pos = (int)__builtin_ctzll(gp);
+                                const int t = evs[pos].y;
+                                const bool pass = m.step_last(dty, t, c);
+                                if (pass | (t >= lim)) {
+                                    // (ticks do not decrease: past the last window
+                                    // no later event passes)
+                                    cpos = pass ? pos : -1;
+                                    ct = t;
+                                    break;
+                                }
+                                gp &= gp - 1ull;
+                            }
+                        } else if (gp) {
                             const int pos = (int)__builtin_ctzll(gp);
                             const int t = evs[pos].y;
-                            const bool pass = m.step_last(dty, t, c);
-                            if (pass | (t >= lim)) {
-                                // (ticks do not decrease: past the last window
-                                // no later event passes)
-                                cpos = pass ? pos : -1;
+                            if (m.step_last(dty, t, c)) {
+                                cpos = pos;
                                 ct = t;
+                            }
+                        }
+                    } else if constexpr (EXACT) {
+                        // a later last-type event may enter a window an earlier one missed
+                        while (gp) {
+                            const int pos = (int)__builtin_ctzll(gp);
+                            const int2 et = evs[pos];
+                            // (et.x differs from dty only on a type-hash collision)
+                            if ((et.x == dty) & m.step_last(et.x, et.y, c)) {
+                                cpos = pos;
+                                ct = et.y;
                                 break;
                             }
+                            if (et.y > lim) break;
                             gp &= gp - 1ull;
                         }
                     } else if (gp) {
-                        const int pos = (int)__builtin_ctzll(gp);
-                        const int t = evs[pos].y;
-                        if (m.step_last(dty, t, c)) {
-                            cpos = pos;
-                            ct = t;
+                        // relaxed: only the first last-type event can pass (a later
+                        // tick cannot pass a test this one failed); the loop skips
+                        // type-hash collisions only
+                        int pos = (int)__builtin_ctzll(gp);
+                        int2 et = evs[pos];
+                        while (et.x != dty && (gp &= gp - 1ull)) {
+                            pos = (int)__builtin_ctzll(gp);
+                            et = evs[pos];
                         }
-                    }
-                } else if constexpr (EXACT) {
-                    // a later last-type event may enter a window an earlier one missed
-                    while (gp) {
-                        const int pos = (int)__builtin_ctzll(gp);
-                        const int2 et = evs[pos];
-                        // (et.x differs from dty only on a type-hash collision)
                         if ((et.x == dty) & m.step_last(et.x, et.y, c)) {
                             cpos = pos;
                             ct = et.y;
-                            break;
                         }
-                        if (et.y > lim) break;
-                        gp &= gp - 1ull;
                     }
-                } else if (gp) {
-                    // relaxed: only the first last-type event can pass (a later
-                    // tick cannot pass a test this one failed); the loop skips
-                    // type-hash collisions only
-                    int pos = (int)__builtin_ctzll(gp);
-                    int2 et = evs[pos];
-                    while (et.x != dty && (gp &= gp - 1ull)) {
-                        pos = (int)__builtin_ctzll(gp);
-                        et = evs[pos];
+                    if (cpos >= 0) {
+                        m.reset();
+                        ++cnt;
+                        lastx = 0;
+                        lastc = i + cpos;
+                        if (NOTE) note(i + cpos, ct);
                     }
-                    if ((et.x == dty) & m.step_last(et.x, et.y, c)) {
-                        cpos = pos;
-                        ct = et.y;
-                    }
-                }
-                if (cpos >= 0) {
-                    m.reset();
-                    ++cnt;
-                    lastx = 0;
-                    lastc = i + cpos;
-                    if (NOTE) note(i + cpos, ct);
                 }
                 unsigned long long pp = remp & upto;
                 remp &= ~upto;
