@@ -135,6 +135,7 @@ template <int N> struct Relaxed {
     }
     // Latest tick list k's test passes at (-1 when empty).
     __device__ __forceinline__ int end_of(int k) const { return dl[k]; }
+    __device__ __forceinline__ void flush(int *) {}
     // Nodes 0..N-2 have wave-uniform types u.ty: scalar tests, rare updates.
     __device__ __forceinline__ bool step_u(int e, int t, const Cand<N> &c, const Prefix<N> &u,
                                            int *)
@@ -224,6 +225,31 @@ template <int N, int D> struct Exact {
         wa[k][D - 1] = mrg ? wa[k][D - 1] : a;
         wb[k][D - 1] = b;
     }
+    // push() for the lanes with p, without a branch: a live window shifted
+    // out (an overflow of the depth class, never expected) is remembered in
+    // ovf and reported by flush()
+    // (an int, so that it stays in a VGPR rather than a lane mask merged at
+    // every branch)
+    int ovf = 0;
+    __device__ __forceinline__ void push_p(int k, int t, int lo, int hi, bool p)
+    {
+        const int a = t + lo + 1, b = t + hi;
+        const bool sh = p & (wb[k][D - 1] < a - 1);
+        ovf |= (sh & (wb[k][0] >= t)) ? 1 : 0;
+#pragma unroll
+        for (int d = 0; d + 1 < D; ++d) {
+            wa[k][d] = sh ? wa[k][d + 1] : wa[k][d];
+            wb[k][d] = sh ? wb[k][d + 1] : wb[k][d];
+        }
+        wa[k][D - 1] = sh ? a : wa[k][D - 1];
+        wb[k][D - 1] = p ? b : wb[k][D - 1];
+    }
+    __device__ __forceinline__ void flush(int *status)
+    {
+        if (__builtin_amdgcn_ballot_w64(ovf != 0) != 0 && __lane_id() == 0)
+            atomicOr(status, ST_INTERNAL);
+        ovf = 0;
+    }
     __device__ __forceinline__ bool step(int e, int t, const Cand<N> &c, bool on, int *status)
     {
         if constexpr (N == 1) {
@@ -273,11 +299,11 @@ template <int N, int D> struct Exact {
                 if (__builtin_expect(e == u.ty[i], 0))
                     if (t <= lm[i - 1]) {
                         lm[i] = t + hm[i];
-                        if (on & hit(i - 1, t)) push(i, t, c.lo[i], c.hi[i], status);
+                        push_p(i, t, c.lo[i], c.hi[i], on & hit(i - 1, t));
                     }
             if (__builtin_expect(e == u.ty[0], 0)) {
                 lm[0] = t + hm[0];
-                if (on) push(0, t, c.lo[0], c.hi[0], status);
+                push_p(0, t, c.lo[0], c.hi[0], on);
             }
         }
     }
@@ -589,6 +615,7 @@ template <int N, bool EXACT, int D> struct MainRun {
         for (; i + WAVE <= ce; i += WAVE) block(std::true_type(), i);
         if (i < ce) block(std::false_type(), i);
         }
+        m.flush(status);
     }
 
     // Per-type dispatch for a wave without a shared prefix: in each block of
