@@ -59,7 +59,7 @@ def test_brute_force_methods_agree():
 INTERVALS_TINY = [(0, 1), (0, 2), (1, 3), (2, 4)]
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7])
 def test_exhaustive_tiny_streams(n):
     """Every stream of length n over 2 types with ticks 0..3 (ties in every
     order), every episode of 1-3 nodes over the tiny interval set."""
