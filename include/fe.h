@@ -307,6 +307,8 @@ typedef struct fe_batch fe_batch;
 typedef struct fe_batch_tuning {
     int32_t seg_events;   /* target events per work item (segment length)    */
     int32_t waves_per_cu; /* persistent waves launched per compute unit      */
+    int32_t waves_per_block; /* work items (one per wave) per workgroup of the
+                             persistent launches: 1, 2, 4 or 8 (0: 4)        */
     double run_ms;        /* measured duration of one fe_batch_run (autotune) */
 } fe_batch_tuning;
 
@@ -324,7 +326,8 @@ int fe_batch_create(fe_ctx *ctx, int32_t R, const fe_job *jobs, fe_batch **out);
 int fe_batch_run(fe_batch *b);
 
 /* Time `reps` runs for each launch shape of a small grid (segment length x
- * persistent waves per CU), keep the fastest; *best receives it.
+ * persistent waves per CU x waves per workgroup), keep the fastest; *best
+ * receives it.
  * Synchronises. */
 int fe_batch_autotune(fe_batch *b, int32_t reps, fe_batch_tuning *best);
 int fe_batch_set_tuning(fe_batch *b, const fe_batch_tuning *t);

@@ -1497,7 +1497,7 @@ struct fe_batch {
     std::vector<Group> groups;
     std::vector<int> rec, orig, tileW;
     int ntiles = 0;
-    fe_batch_tuning tun{32768, 16, 0.0};
+    fe_batch_tuning tun{32768, 16, WPB, 0.0};
     // device
     Buf pk, origd, tileWd, tilesd, jobsd, itemsd, listsd, lamd, tbld, flagsr, flagsx, qctr, deepd;
     struct Level {
@@ -1669,7 +1669,7 @@ int batch_plan(fe_batch *b)
     launch_fill(P<int>(b->flagsx), 0, (int64_t)T * WAVE, s);
     HIPCHK(c, hipStreamSynchronize(s));
 
-    const int grid = std::max(1, b->ncu * b->tun.waves_per_cu / WPB);
+    const int grid = std::max(1, b->ncu * b->tun.waves_per_cu / b->tun.waves_per_block);
     int *lists_d = P<int>(b->listsd);
     int q = 0;
     for (const LvPlan &L : lp) {
@@ -1686,6 +1686,7 @@ int batch_plan(fe_batch *b)
         d.tbl = P<int2>(b->tbld);
         d.status = P<int>(c->status);
         d.sparse = c->param[FE_PARAM_TYPE_DISPATCH] != 0;
+        d.wpb = b->tun.waves_per_block;
         const int q0 = q;
         int nq = 1;
         for (int dd = 0; dd < NDCLS; ++dd) nq += L.n_ex[dd] > 0;
@@ -1860,10 +1861,13 @@ extern "C" int fe_batch_run(fe_batch *b)
 
 extern "C" int fe_batch_set_tuning(fe_batch *b, const fe_batch_tuning *t)
 {
-    if (!b || !t || t->seg_events < 256 || t->waves_per_cu < 1 || t->waves_per_cu > 64)
+    const int wpb = t ? (t->waves_per_block ? t->waves_per_block : WPB) : 0;
+    if (!b || !t || t->seg_events < 256 || t->waves_per_cu < 1 || t->waves_per_cu > 64 ||
+        wpb < 1 || wpb > PERSIST_WPB_MAX || (wpb & (wpb - 1)))
         return FE_EINVAL;
     b->tun.seg_events = t->seg_events;
     b->tun.waves_per_cu = t->waves_per_cu;
+    b->tun.waves_per_block = wpb;
     return batch_plan(b);
 }
 
@@ -1881,14 +1885,17 @@ extern "C" int fe_batch_autotune(fe_batch *b, int32_t reps, fe_batch_tuning *bes
     int rc;
     const int segs[] = {8192, 16384, 32768, 65536, 131072};
     const int wpcs[] = {8, 16, 32};
-    fe_batch_tuning top{0, 0, 1e30};
+    const int wpbs[] = {2, 4, 8};
+    fe_batch_tuning top{0, 0, 0, 1e30};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     for (int sg : segs)
-        for (int wp : wpcs) {
+        for (int wp : wpcs)
+        for (int wb : wpbs) {
             b->tun.seg_events = sg;
             b->tun.waves_per_cu = wp;
+            b->tun.waves_per_block = wb;
             if ((rc = batch_plan(b))) return rc;
             if ((rc = fe_batch_run(b))) return rc;  // warm-up
             HIPCHK(c, hipEventRecord(e0, c->stream));
@@ -1898,7 +1905,7 @@ extern "C" int fe_batch_autotune(fe_batch *b, int32_t reps, fe_batch_tuning *bes
             HIPCHK(c, hipEventSynchronize(e1));
             float ms = 0.f;
             HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-            if (ms / reps < top.run_ms) top = fe_batch_tuning{sg, wp, ms / reps};
+            if (ms / reps < top.run_ms) top = fe_batch_tuning{sg, wp, wb, ms / reps};
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -2196,6 +2203,7 @@ int server_launch(fe_server *sv, fe_server::Lane &ln)
     d.tbl = (int2 *)(ar + o_tbl);
     d.status = P<int>(ln.statd);
     d.sparse = c->param[FE_PARAM_TYPE_DISPATCH] != 0;
+    d.wpb = WPB;
     int *lists_d = (int *)(ar + o_lists);
     int *fr = (int *)(ar + o_fr), *fx = (int *)(ar + o_fx), *qc = (int *)(ar + o_q);
     const int grid = std::max(1, sv->ncu * sv->cfg.waves_per_cu / WPB);

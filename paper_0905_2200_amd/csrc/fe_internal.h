@@ -65,6 +65,7 @@ struct BatchDev {
     int *flags;
     int *status;
     int sparse;  // per-type dispatch for the bulk of each item
+    int wpb;     // waves per block of the persistent launch (1..PERSIST_WPB_MAX)
 };
 
 // Exact count of candidates of the deep class: one wave per tile over the
@@ -88,6 +89,8 @@ struct DeepArgs {
 };
 // window rings one deep launch may hold by default (bytes)
 constexpr int64_t DEEP_SCRATCH = (int64_t)256 << 20;
+
+constexpr int PERSIST_WPB_MAX = 8;
 
 // launchers (fe_kernels.hip)
 void launch_fill(int *p, int v, int64_t n, hipStream_t s);

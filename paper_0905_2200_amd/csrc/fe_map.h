@@ -1081,11 +1081,14 @@ __global__ __launch_bounds__(WAVE *WPB) void k_resume(const int *__restrict__ id
 // items of many recordings from a queue (heaviest first) until it is empty.
 // In the exact pass only candidates that survived the relaxed pass count;
 // the others get -1.
+// (blocks of b.wpb waves, up to PERSIST_WPB_MAX; each wave's 1 KiB of
+// dispatch scratch in dynamic LDS)
 template <int N, bool EXACT, int D, bool SPARSE>
-__global__ __launch_bounds__(WAVE *WPB) void k_persist(BatchDev b)
+__global__ __launch_bounds__(WAVE *PERSIST_WPB_MAX) void k_persist(BatchDev b)
 {
-    __shared__ unsigned long long s_tm[WPB][WAVE];
-    __shared__ int2 s_ev[WPB][WAVE];
+    extern __shared__ unsigned long long s_pdyn[];
+    unsigned long long *s_tm = s_pdyn + (threadIdx.x >> 6) * 2 * WAVE;
+    int2 *s_ev = (int2 *)(s_tm + WAVE);
     const int lane = __lane_id();
     for (;;) {
         int it = 0;
@@ -1119,8 +1122,8 @@ __global__ __launch_bounds__(WAVE *WPB) void k_persist(BatchDev b)
         a.cmask = nullptr;
         a.gids = jb.ids;
         a.gticks = jb.ticks;
-        a.tm = s_tm[threadIdx.x >> 6];
-        a.evs = s_ev[threadIdx.x >> 6];
+        a.tm = s_tm;
+        a.evs = s_ev;
         a.hashx = false;
         map_item<N, EXACT, D, SPARSE>(a, o, valid);
     }
@@ -1401,12 +1404,13 @@ void persist_n(const BatchDev &b, int grid, const int *ctiles, int nct, hipStrea
             hipLaunchKernelGGL((k_persist_fixup<N, EXACT, D>), dim3((nct + WPB - 1) / WPB),
                                dim3(WAVE * WPB), 0, s, b, ctiles, nct);
     } else {
+        const size_t lds = (size_t)b.wpb * 2 * WAVE * sizeof(unsigned long long);
         if (b.sparse)
-            hipLaunchKernelGGL((k_persist<N, EXACT, D, true>), dim3(grid), dim3(WAVE * WPB), 0,
-                               s, b);
+            hipLaunchKernelGGL((k_persist<N, EXACT, D, true>), dim3(grid), dim3(WAVE * b.wpb),
+                               lds, s, b);
         else
-            hipLaunchKernelGGL((k_persist<N, EXACT, D, false>), dim3(grid), dim3(WAVE * WPB), 0,
-                               s, b);
+            hipLaunchKernelGGL((k_persist<N, EXACT, D, false>), dim3(grid), dim3(WAVE * b.wpb),
+                               lds, s, b);
     }
 }
 

@@ -81,7 +81,7 @@ class _Job(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("seg_events", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-                ("run_ms", ctypes.c_double)]
+                ("waves_per_block", ctypes.c_int32), ("run_ms", ctypes.c_double)]
 
 
 class _ServerCfg(ctypes.Structure):
@@ -431,16 +431,18 @@ class Batch:
     def autotune(self, reps=2):
         t = _Tuning()
         self.ctx._check(self.ctx._call(lib().fe_batch_autotune, self.h, int(reps), ctypes.byref(t)))
-        return {"seg_events": t.seg_events, "waves_per_cu": t.waves_per_cu, "run_ms": t.run_ms}
+        return {"seg_events": t.seg_events, "waves_per_cu": t.waves_per_cu,
+                "waves_per_block": t.waves_per_block, "run_ms": t.run_ms}
 
-    def set_tuning(self, seg_events, waves_per_cu):
-        t = _Tuning(int(seg_events), int(waves_per_cu), 0.0)
+    def set_tuning(self, seg_events, waves_per_cu, waves_per_block=0):
+        t = _Tuning(int(seg_events), int(waves_per_cu), int(waves_per_block), 0.0)
         self.ctx._check(self.ctx._call(lib().fe_batch_set_tuning, self.h, ctypes.byref(t)))
 
     def tuning(self):
         t = _Tuning()
         self.ctx._check(lib().fe_batch_get_tuning(self.h, ctypes.byref(t)))
-        return {"seg_events": t.seg_events, "waves_per_cu": t.waves_per_cu, "run_ms": t.run_ms}
+        return {"seg_events": t.seg_events, "waves_per_cu": t.waves_per_cu,
+                "waves_per_block": t.waves_per_block, "run_ms": t.run_ms}
 
     def close(self):
         if getattr(self, "h", None):

@@ -44,13 +44,14 @@ def _dev(ctx, recs):
     return out
 
 
-@pytest.mark.parametrize("seg_events", [256, 2048, 32768])
-def test_batch_matches_oracle(ctx, fe, seg_events):
+@pytest.mark.parametrize("seg_events,wpb", [(256, 4), (2048, 1), (2048, 8), (32768, 2)])
+def test_batch_matches_oracle(ctx, fe, seg_events, wpb):
     recs = _small_batch()
-    banner("batch of %d, seg_events=%d" % (len(recs), seg_events))
+    banner("batch of %d, seg_events=%d, waves_per_block=%d" % (len(recs), seg_events, wpb))
     dev = _dev(ctx, recs)
     b = fe.Batch(ctx, dev)
-    b.set_tuning(seg_events, 8)
+    b.set_tuning(seg_events, 8, wpb)
+    assert b.tuning()["waves_per_block"] == wpb
     for rep in range(2):  # replays must give the same result
         b.run()
         ctx.sync()
@@ -67,11 +68,21 @@ def test_batch_equals_alone_and_autotune(ctx, fe):
     b = fe.Batch(ctx, dev)
     t = b.autotune(reps=1)
     banner("autotuned %s" % t)
-    assert t["seg_events"] > 0 and t["waves_per_cu"] > 0
+    assert t["seg_events"] > 0 and t["waves_per_cu"] > 0 and t["waves_per_block"] in (2, 4, 8)
     b.run()
     ctx.sync()
     for r, d in enumerate(dev):
         up, ex, ns = ctx.count_two_pass(d["ids"], d["ticks"], d["num_types"], d["cand"], d["theta"])
         assert (b.upper[r].cpu().numpy() == up.cpu().numpy()).all(), r
         assert (b.exact[r].cpu().numpy() == ex.cpu().numpy()).all(), r
+    b.close()
+
+
+def test_tuning_rejects_bad_shapes(ctx, fe):
+    b = fe.Batch(ctx, _dev(ctx, _small_batch(R=2, seed=5)))
+    for seg, wp, wb in [(128, 8, 4), (4096, 0, 4), (4096, 8, 3), (4096, 8, 16)]:
+        with pytest.raises(fe.FeError):
+            b.set_tuning(seg, wp, wb)
+    b.set_tuning(4096, 8)  # 0 waves per block: the default
+    assert b.tuning()["waves_per_block"] == 4
     b.close()
