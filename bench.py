@@ -84,6 +84,7 @@ def bench_mining(args, fe, synth, torch):
     log("workload: %s; n=%d theta=%d" % (s["name"], n, theta))
     ctx = fe.Context(0)
     ctx.set_param(fe.PARAM_TYPE_DISPATCH, args.type_dispatch)
+    ctx.set_param(fe.PARAM_SHARED_LISTS, args.shared_lists)
     if args.elimination is not None:
         ctx.set_param(fe.PARAM_ELIMINATION, args.elimination)
     if args.host_tiling is not None:
@@ -588,6 +589,8 @@ def main():
                          "library's per-level rule (default: the library's default)")
     ap.add_argument("--host-tiling", type=int, default=None, choices=[0, 1],
                     help="mining: 1 = tile each level on the host, 0 = on the device")
+    ap.add_argument("--shared-lists", type=int, default=1, choices=[0, 1],
+                    help="exact waves of join siblings keep lists 0..N-3 once (0 = per lane)")
     ap.add_argument("--type-dispatch", type=int, default=1, choices=[0, 1],
                     help="per-type dispatch for shared-prefix waves (0 = every event)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,

@@ -141,8 +141,15 @@ typedef enum fe_param {
                                 thousandths of the exact pass's (default 800,
                                 measured on the mining workload's levels 3
                                 and 4); used by FE_PARAM_ELIMINATION = 2      */
-    FE_PARAM_SAMPLE_MIN = 14  /* smallest level sampled by FE_PARAM_ELIMINATION
+    FE_PARAM_SAMPLE_MIN = 14, /* smallest level sampled by FE_PARAM_ELIMINATION
                                 = 2 (default 131072 candidates)                */
+    FE_PARAM_SHARED_LISTS = 15 /* 1 (default) = exact whole-stream counting of
+                                a tile whose candidates share every node but
+                                the last and every hop but the last (join
+                                siblings, N >= 3) keeps lists 0..N-3 once per
+                                tile, each entry with the start index of its
+                                newest chain; 0 = per-candidate lists (same
+                                counts)                                       */
 } fe_param;
 
 typedef struct fe_ctx fe_ctx;

@@ -102,7 +102,7 @@ double now_ms()
 
 }  // namespace
 
-constexpr int NPARAM = 15;
+constexpr int NPARAM = 16;
 
 struct fe_ctx {
     int device = 0;
@@ -110,7 +110,7 @@ struct fe_ctx {
     bool own_stream = false;
     std::string err;
     int64_t param[NPARAM] = {0, 4096, 1024, 1, 0, 1, -8136, 19504, 2, 0, 0, 9232, 5798, 800,
-                             131072};
+                             131072, 1};
     fe_stats stats{};
     // workspace
     Buf keys, hist, wmax, pk, orig, tileW, lam, tbl, flags, sel, nsel, status, small, cmask;
@@ -461,6 +461,7 @@ int launch_groups(fe_ctx *c, const int *ids, const int *ticks, const StreamInfo 
         }
         g.sparse = c->param[FE_PARAM_TYPE_DISPATCH] != 0;
         g.hashx = si.num_types <= 64;
+        g.shlists = c->param[FE_PARAM_SHARED_LISTS] != 0;
         c->stats.map_launches++;
         if (rs) {
             char rname[40];

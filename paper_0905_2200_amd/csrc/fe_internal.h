@@ -31,6 +31,7 @@ struct MapGroup {
     int P;
     int sparse;  // shared-prefix waves use per-type dispatch
     int hashx;   // every type id is below 64: the type hash (id & 63) is the id
+    int shlists; // exact, P = 1: waves of join siblings keep lists 0..N-3 once
 };
 
 // Batched counting (many recordings): one descriptor per recording and per

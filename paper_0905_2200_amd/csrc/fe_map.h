@@ -195,6 +195,17 @@ template <int N, int D> struct Exact {
                 wb[k][d] = GONE;
             }
     }
+    // reset() for the lanes with p, without a branch
+    __device__ __forceinline__ void reset_p(bool p)
+    {
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k)
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                wa[k][d] = p ? EMPTY : wa[k][d];
+                wb[k][d] = p ? GONE : wb[k][d];
+            }
+    }
     // t in [wa, wb] as one unsigned compare per window: t - wa <= wb - wa
     // (mod 2^32).  Live windows have wa <= wb and ticks below 2^30; an unused
     // slot (EMPTY, GONE) gives wb - wa = 1 and t - wa >= 2^31.
@@ -817,6 +828,239 @@ __device__ __forceinline__ bool shared_prefix(const Cand<N> &c, bool valid, Pref
     }
 }
 
+// Hop intervals 0..N-3 shared by every valid lane (wave-uniform values).
+template <int N> struct UHops {
+    int lo[N > 2 ? N - 2 : 1];
+    int hi[N > 2 ? N - 2 : 1];
+};
+
+template <int N>
+__device__ __forceinline__ bool shared_hops(const Cand<N> &c, bool valid, UHops<N> &h)
+{
+    if constexpr (N < 3) {
+        return false;
+    } else {
+        const unsigned long long vm = __ballot(valid);
+        if (vm == 0) return false;
+        const int first = __ffsll((long long)vm) - 1;
+        bool same = true;
+#pragma unroll
+        for (int k = 0; k < N - 2; ++k) {
+            h.lo[k] = uniform(__shfl(c.lo[k], first));
+            h.hi[k] = uniform(__shfl(c.hi[k], first));
+            same &= __ballot(valid & ((c.lo[k] != h.lo[k]) | (c.hi[k] != h.hi[k]))) == 0;
+        }
+        return same;
+    }
+}
+
+// Exact whole-stream Map of a wave whose lanes share the types of nodes
+// 0..N-2 and the hops 0..N-3 (the join siblings of one frequent episode:
+// they differ only in the last node and hop).  Lists 0..N-3 then receive
+// the same events in every lane, except that a lane's completion empties
+// its lists; so they are kept once per wave.  Each entry (tick, s) carries
+// s, the stream index at which the newest chain of hop-passing events
+// behind it starts (node 0: the event's own index); a lane's list holds
+// exactly the entries with s after its last completion (by induction over
+// the nodes: a chain lies after the completion iff its first event does).
+// Along a list s does not decrease (a later event's newest predecessor in
+// range is no older), so whether a node-k event at t passes hop k-1 -- an
+// entry of list k-1 in [t - hi, t - lo - 1] -- and with which s is decided
+// by the newest entry at or before t - lo - 1 alone.
+//   Per lane remain list N-2 as windows (its hop differs by lane), the last
+// node's test, the count and the index of the last completion.  In a block
+// of 64 events (one per lane), node by node (so that the block's earlier
+// events are in place), each node-k event enters list k (node 0: always;
+// node k >= 1: when it passes against list k-1).  The node N-2 events that
+// pass are list N-2's entries: they close spans as in the per-type dispatch
+// (sparse_t), and enter a lane's windows when their s is after its last
+// completion.  A block where no lane's list N-2 passes a tick from the
+// block's first on and no entry arrives is done after the list updates.
+//   Lists 0..N-3 are rings of the 64 newest entries held across the lanes
+// of two registers (lane q: slot q), oldest to newest from the next slot to
+// write, unused slots at tick EMPTY.  Ticks do not decrease along a ring,
+// so the entries at or before a tick are its first c slots in that order
+// (c: a ballot's popcount) and the newest of them is the c-th.  Overwriting
+// an entry that could still pass a later test (its tick within hi of the
+// block's first tick) ends the method with false: the caller then counts
+// the tile with the general dispatch.
+template <int N, int D, bool HX>
+__device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> &c,
+                         const Prefix<N> &u, const UHops<N> &uh, unsigned long long *tm,
+                         int2 *evs, int2 *scr, int *status, int &cnt_out)
+{
+    static_assert(N >= 3, "lists 0..N-3 must exist");
+    constexpr int NR = N - 2;
+    const int lane = __lane_id();
+    const int lane4 = lane * 4;
+    const int dty = c.ty[N - 1];
+    const int dh = dty & 63;
+    Exact<2, D> w;  // list N-2
+    w.reset();
+    int cnt = 0, rr = -1;
+    int rt[NR], rs[NR];  // rings: tick and s of slot `lane`
+    int hd[NR], nt[NR];  // entries ever entered, newest entry's tick
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        rt[k] = EMPTY;
+        rs[k] = 0;
+        hd[k] = 0;
+        nt[k] = GONE;
+    }
+    // wave-uniform: hm the largest hi of hop N-2, lm >= every lane's end_of
+    int hm = c.hi[N - 2];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(hm, off);
+        hm = o > hm ? o : hm;
+    }
+    hm = uniform(hm);
+    int lm = GONE;
+    // an entry overwritten while it could still pass a later test (the
+    // results are then discarded; every index stays within the rings)
+    bool rovf = false;
+    for (int cb = 0; cb < n; cb += EV_CHUNK) {
+        const int ce = n - cb > EV_CHUNK ? cb + EV_CHUNK : n;
+        const EvBuf eb(ids, ticks, cb, ce);
+        int nid, ntk;
+        eb.load(0, lane4, nid, ntk);
+        // (full blocks and the final partial one are separate copies)
+        auto block = [&](auto full_tag, int i) {
+            constexpr bool FULL = decltype(full_tag)::value;
+            const int id = nid, tk = ntk;
+            eb.load(i - cb + WAVE, lane4, nid, ntk);
+            const int tk0 = __builtin_amdgcn_readfirstlane(tk);
+            const unsigned long long vm = FULL ? ~0ull : (1ull << (ce - i)) - 1ull;
+            // node 0: every event enters list 0 with s = its index
+            const bool is0 = FULL ? id == u.ty[0] : (id == u.ty[0]) & (lane < ce - i);
+            const unsigned long long m0 = __builtin_amdgcn_ballot_w64(is0);
+            if (m0) {
+                const int q = hd[0];
+                const int c0 = __popcll(m0);
+                // the newest entry overwritten (the oldest ones have lower ticks)
+                if (q + c0 > WAVE &&
+                    __builtin_amdgcn_readlane(rt[0], (q + c0 - 1) & (WAVE - 1)) >=
+                        tk0 - uh.hi[0])
+                    rovf = true;
+                // the block's node-0 events in order to scr[0..c0), then to
+                // ring slots q, q+1, ... (other lanes write scr[WAVE], unread)
+                const int rank = __builtin_amdgcn_mbcnt_hi(
+                    (unsigned)(m0 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m0, 0u));
+                scr[is0 ? rank : WAVE] = make_int2(tk, i + lane);
+                __builtin_amdgcn_wave_barrier();
+                const int r = (lane - q) & (WAVE - 1);
+                const bool take = r < c0;
+                const int2 e = scr[take ? r : WAVE];
+                rt[0] = take ? e.x : rt[0];
+                rs[0] = take ? e.y : rs[0];
+                hd[0] = q + c0;
+                nt[0] = __builtin_amdgcn_readlane(tk, 63 - __clzll(m0));
+            }
+            unsigned long long remb = 0;
+            int sv = 0;
+#pragma unroll
+            for (int k = 1; k <= N - 2; ++k) {
+                // (skipped when no entry of list k-1 can lie in range of the
+                // block's events, most blocks)
+                if (nt[k - 1] < tk0 - uh.hi[k - 1]) continue;
+                unsigned long long pk = __builtin_amdgcn_ballot_w64(id == u.ty[k]);
+                if (!FULL) pk &= vm;
+                const int base = hd[k - 1] >= WAVE ? hd[k - 1] - 1 : -1;
+                while (pk) {
+                    const int x = (int)__builtin_ctzll(pk);
+                    pk ^= 1ull << x;
+                    const int t = __builtin_amdgcn_readlane(tk, x);
+                    // entries at or before t - lo - 1: the first popcount in ring order
+                    const unsigned long long le =
+                        __builtin_amdgcn_ballot_w64(rt[k - 1] <= t - uh.lo[k - 1] - 1);
+                    if (le == 0) continue;
+                    const int q = (base + __popcll(le)) & (WAVE - 1);
+                    if (__builtin_amdgcn_readlane(rt[k - 1], q) < t - uh.hi[k - 1]) continue;
+                    const int s = __builtin_amdgcn_readlane(rs[k - 1], q);
+                    if (k < N - 2) {
+                        const int qk = hd[k] & (WAVE - 1);
+                        if (hd[k] >= WAVE && __builtin_amdgcn_readlane(rt[k], qk) >= tk0 - uh.hi[k])
+                            rovf = true;
+                        const bool at = lane == qk;
+                        rt[k] = at ? t : rt[k];
+                        rs[k] = at ? s : rs[k];
+                        ++hd[k];
+                        nt[k] = t;
+                    } else {
+                        remb |= 1ull << x;
+                        sv = lane == x ? s : sv;
+                    }
+                }
+            }
+            if (remb == 0)
+                if (lm < tk0) return;
+            // type table of the block for the last node's search
+            tm[lane] = 0;
+            evs[lane] = make_int2(id, tk);
+            if (FULL || lane < ce - i) atomicOr(&tm[id & 63], 1ull << lane);
+            unsigned long long ml = tm[dh];
+            for (;;) {
+                // span: positions up to the lowest entry of list N-2 (all if none)
+                const unsigned long long rb1 = remb - 1ull;
+                const unsigned long long upto = remb ? (remb ^ rb1) : ~0ull;
+                unsigned long long gp = 0;
+                int lim = GONE;
+                if (lm >= tk0) {
+                    gp = ml & upto;
+                    lim = w.end_of(0);
+                    if (lim < tk0) gp = 0;
+                }
+                ml &= ~upto;
+                int cpos = -1;
+                if (__builtin_amdgcn_ballot_w64(gp != 0) != 0) {
+                    if constexpr (HX) {
+                        while (gp) {
+                            const int pos = (int)__builtin_ctzll(gp);
+                            const int t = evs[pos].y;
+                            const bool pass = w.hit(0, t);
+                            if (pass | (t >= lim)) {
+                                cpos = pass ? pos : -1;
+                                break;
+                            }
+                            gp &= gp - 1ull;
+                        }
+                    } else {
+                        while (gp) {
+                            const int pos = (int)__builtin_ctzll(gp);
+                            const int2 et = evs[pos];
+                            if ((et.x == dty) & w.hit(0, et.y)) {
+                                cpos = pos;
+                                break;
+                            }
+                            if (et.y > lim) break;
+                            gp &= gp - 1ull;
+                        }
+                    }
+                }
+                if (__builtin_amdgcn_ballot_w64(cpos >= 0) != 0) {
+                    const bool done = cpos >= 0;
+                    w.reset_p(done);
+                    cnt += done ? 1 : 0;
+                    rr = done ? i + cpos : rr;
+                }
+                if (!remb) break;
+                const int x = (int)__builtin_ctzll(remb);
+                const int t = __builtin_amdgcn_readlane(tk, x);
+                const bool on = __builtin_amdgcn_readlane(sv, x) > rr;
+                w.push_p(0, t, c.lo[N - 2], c.hi[N - 2], on);
+                if (__builtin_amdgcn_ballot_w64(on) != 0) lm = t + hm;
+                remb &= rb1;
+            }
+        };
+        int i = cb;
+        for (; i + WAVE <= ce; i += WAVE) block(std::true_type(), i);
+        if (i < ce) block(std::false_type(), i);
+    }
+    w.flush(status);
+    cnt_out = cnt;
+    return !rovf;
+}
+
 // Everything one work item (a tile of 64 candidates over segment p of P)
 // needs; shared by the per-group launch (k_map) and the persistent batched
 // launch (k_persist).
@@ -967,8 +1211,21 @@ __global__ __launch_bounds__(WAVE *WPB) void k_map1(const int *__restrict__ ids_
         __shared__ int2 s_ev[WPB][WAVE];
         const int wv = threadIdx.x >> 6;
         bool done = false;
+        if constexpr (EXACT && N >= 3) {
+            __shared__ int2 s_scr[WPB][WAVE + 1];
+            UHops<N> uh;
+            if (uni && g.shlists && shared_hops<N>(cd, o >= 0, uh)) {
+                if (g.hashx)
+                    done = sparse_u<N, D, true>(ids_, ticks_, g.n, cd, u, uh, s_tm[wv], s_ev[wv],
+                                                s_scr[wv], g.status, r.cnt);
+                else
+                    done = sparse_u<N, D, false>(ids_, ticks_, g.n, cd, u, uh, s_tm[wv],
+                                                 s_ev[wv], s_scr[wv], g.status, r.cnt);
+                if (!done) r.cnt = 0;
+            }
+        }
         if constexpr (N >= 2) {
-            if (uni) {
+            if (uni && !done) {
                 r.template sparse<false>(ids_, ticks_, 0, g.n, cd, u, s_tm[wv], s_ev[wv],
                                          g.status, g.hashx != 0);
                 done = true;

@@ -20,7 +20,7 @@ FE_EXACT, FE_RELAXED = 0, 1
 PARAM_SEGMENTS, PARAM_TARGET_WAVES, PARAM_MIN_SEG_EVENTS, PARAM_CONCAT_TREE, PARAM_TIMING, \
     PARAM_TYPE_DISPATCH, PARAM_CROSSOVER_A, PARAM_CROSSOVER_B, PARAM_ELIMINATION, \
     PARAM_HOST_TILING, PARAM_KEEP_CANDIDATES, PARAM_CROSSOVER_A_RELAXED, \
-    PARAM_CROSSOVER_B_RELAXED, PARAM_PASS1_COST, PARAM_SAMPLE_MIN = range(15)
+    PARAM_CROSSOVER_B_RELAXED, PARAM_PASS1_COST, PARAM_SAMPLE_MIN, PARAM_SHARED_LISTS = range(16)
 
 STATUS_NAMES = {0: "FE_OK", 1: "FE_EINVAL", 2: "FE_ENOMEM", 3: "FE_EDEVICE",
                 4: "FE_EUNSORTED", 5: "FE_ERANGE", 6: "FE_EBUSY", 7: "FE_EINTERNAL"}
