@@ -877,13 +877,16 @@ __device__ __forceinline__ bool shared_hops(const Cand<N> &c, bool valid, UHops<
 // completion.  A block where no lane's list N-2 passes a tick from the
 // block's first on and no entry arrives is done after the list updates.
 //   Lists 0..N-3 are rings of the 64 newest entries held across the lanes
-// of two registers (lane q: slot q), oldest to newest from the next slot to
-// write, unused slots at tick EMPTY.  Ticks do not decrease along a ring,
-// so the entries at or before a tick are its first c slots in that order
-// (c: a ballot's popcount) and the newest of them is the c-th.  Overwriting
-// an entry that could still pass a later test (its tick within hi of the
-// block's first tick) ends the method with false: the caller then counts
-// the tile with the general dispatch.
+// of three registers (lane q: slot q), oldest to newest from the next slot
+// to write; an entry is kept as the first and last tick its hop test passes
+// at (tick + lo + 1, tick + hi) with its s, unused slots first passing at
+// EMPTY.  Ticks do not decrease along a ring, so the entries that pass from
+// a tick t on or earlier are its first c slots in that order (c: a
+// ballot's popcount), and the newest of them passes at t iff its last
+// passing tick is at least t.  Overwriting an entry that could still pass a
+// later test (its last passing tick at or after the block's first tick)
+// ends the method with false: the caller then counts the tile with the
+// general dispatch.
 template <int N, int D, bool HX>
 __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> &c,
                          const Prefix<N> &u, const UHops<N> &uh, unsigned long long *tm,
@@ -898,14 +901,17 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
     Exact<2, D> w;  // list N-2
     w.reset();
     int cnt = 0, rr = -1;
-    int rt[NR], rs[NR];  // rings: tick and s of slot `lane`
-    int hd[NR], nt[NR];  // entries ever entered, newest entry's tick
+    // rings, slot `lane`: the first and last tick the entry's hop test
+    // passes at (tick + lo_k + 1, tick + hi_k) and its s
+    int rl[NR], rh[NR], rs[NR];
+    int hd[NR], nh[NR];  // entries ever entered, newest entry's last passing tick
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-        rt[k] = EMPTY;
+        rl[k] = EMPTY;
+        rh[k] = GONE;
         rs[k] = 0;
         hd[k] = 0;
-        nt[k] = GONE;
+        nh[k] = GONE;
     }
     // wave-uniform: hm the largest hi of hop N-2, lm >= every lane's end_of
     int hm = c.hi[N - 2];
@@ -939,8 +945,7 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                 const int c0 = __popcll(m0);
                 // the newest entry overwritten (the oldest ones have lower ticks)
                 if (q + c0 > WAVE &&
-                    __builtin_amdgcn_readlane(rt[0], (q + c0 - 1) & (WAVE - 1)) >=
-                        tk0 - uh.hi[0])
+                    __builtin_amdgcn_readlane(rh[0], (q + c0 - 1) & (WAVE - 1)) >= tk0)
                     rovf = true;
                 // the block's node-0 events in order to scr[0..c0), then to
                 // ring slots q, q+1, ... (other lanes write scr[WAVE], unread)
@@ -951,10 +956,11 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                 const int r = (lane - q) & (WAVE - 1);
                 const bool take = r < c0;
                 const int2 e = scr[take ? r : WAVE];
-                rt[0] = take ? e.x : rt[0];
+                rl[0] = take ? e.x + uh.lo[0] + 1 : rl[0];
+                rh[0] = take ? e.x + uh.hi[0] : rh[0];
                 rs[0] = take ? e.y : rs[0];
                 hd[0] = q + c0;
-                nt[0] = __builtin_amdgcn_readlane(tk, 63 - __clzll(m0));
+                nh[0] = __builtin_amdgcn_readlane(tk, 63 - __clzll(m0)) + uh.hi[0];
             }
             unsigned long long remb = 0;
             int sv = 0;
@@ -962,7 +968,7 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
             for (int k = 1; k <= N - 2; ++k) {
                 // (skipped when no entry of list k-1 can lie in range of the
                 // block's events, most blocks)
-                if (nt[k - 1] < tk0 - uh.hi[k - 1]) continue;
+                if (nh[k - 1] < tk0) continue;
                 unsigned long long pk = __builtin_amdgcn_ballot_w64(id == u.ty[k]);
                 if (!FULL) pk &= vm;
                 const int base = hd[k - 1] >= WAVE ? hd[k - 1] - 1 : -1;
@@ -970,22 +976,23 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                     const int x = (int)__builtin_ctzll(pk);
                     pk ^= 1ull << x;
                     const int t = __builtin_amdgcn_readlane(tk, x);
-                    // entries at or before t - lo - 1: the first popcount in ring order
-                    const unsigned long long le =
-                        __builtin_amdgcn_ballot_w64(rt[k - 1] <= t - uh.lo[k - 1] - 1);
+                    // entries whose test passes from t on or earlier: the first
+                    // popcount in ring order
+                    const unsigned long long le = __builtin_amdgcn_ballot_w64(rl[k - 1] <= t);
                     if (le == 0) continue;
                     const int q = (base + __popcll(le)) & (WAVE - 1);
-                    if (__builtin_amdgcn_readlane(rt[k - 1], q) < t - uh.hi[k - 1]) continue;
+                    if (__builtin_amdgcn_readlane(rh[k - 1], q) < t) continue;
                     const int s = __builtin_amdgcn_readlane(rs[k - 1], q);
                     if (k < N - 2) {
                         const int qk = hd[k] & (WAVE - 1);
-                        if (hd[k] >= WAVE && __builtin_amdgcn_readlane(rt[k], qk) >= tk0 - uh.hi[k])
+                        if (hd[k] >= WAVE && __builtin_amdgcn_readlane(rh[k], qk) >= tk0)
                             rovf = true;
                         const bool at = lane == qk;
-                        rt[k] = at ? t : rt[k];
+                        rl[k] = at ? t + uh.lo[k] + 1 : rl[k];
+                        rh[k] = at ? t + uh.hi[k] : rh[k];
                         rs[k] = at ? s : rs[k];
                         ++hd[k];
-                        nt[k] = t;
+                        nh[k] = t + uh.hi[k];
                     } else {
                         remb |= 1ull << x;
                         sv = lane == x ? s : sv;
