@@ -76,6 +76,12 @@ struct EvBuf {
         id = __builtin_amdgcn_raw_buffer_load_b32(ri, lane4, rel * 4, 0);
         tk = __builtin_amdgcn_raw_buffer_load_b32(rt, lane4, rel * 4, 0);
     }
+    // the same, at byte offset boff = 4 rel
+    __device__ __forceinline__ void load_b(int boff, int lane4, int &id, int &tk) const
+    {
+        id = __builtin_amdgcn_raw_buffer_load_b32(ri, lane4, boff, 0);
+        tk = __builtin_amdgcn_raw_buffer_load_b32(rt, lane4, boff, 0);
+    }
 };
 
 template <int N> struct Cand {
@@ -903,14 +909,16 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
     int cnt = 0, rr = -1;
     // rings, slot `lane`: the first and last tick the entry's hop test
     // passes at (tick + lo_k + 1, tick + hi_k) and its s
+    // (a ring starts full of unused slots that pass from GONE and to GONE:
+    // counted by every search, oldest in ring order, never passing at a tick)
     int rl[NR], rh[NR], rs[NR];
-    int hd[NR], nh[NR];  // entries ever entered, newest entry's last passing tick
+    int hd[NR], nh[NR];  // slots ever written + 64, newest entry's last passing tick
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-        rl[k] = EMPTY;
+        rl[k] = GONE;
         rh[k] = GONE;
         rs[k] = 0;
-        hd[k] = 0;
+        hd[k] = WAVE;
         nh[k] = GONE;
     }
     // wave-uniform: hm the largest hi of hop N-2, lm >= every lane's end_of
@@ -922,19 +930,20 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
     }
     hm = uniform(hm);
     int lm = GONE;
-    // an entry overwritten while it could still pass a later test (the
-    // results are then discarded; every index stays within the rings)
-    bool rovf = false;
+    // set in the lane of a slot whose entry was overwritten while it could
+    // still pass a later test (the results are then discarded; every index
+    // stays within the rings)
+    int ovr = 0;
     for (int cb = 0; cb < n; cb += EV_CHUNK) {
         const int ce = n - cb > EV_CHUNK ? cb + EV_CHUNK : n;
         const EvBuf eb(ids, ticks, cb, ce);
         int nid, ntk;
         eb.load(0, lane4, nid, ntk);
         // (full blocks and the final partial one are separate copies)
-        auto block = [&](auto full_tag, int i) {
+        auto block = [&](auto full_tag, int i, int boff) {
             constexpr bool FULL = decltype(full_tag)::value;
             const int id = nid, tk = ntk;
-            eb.load(i - cb + WAVE, lane4, nid, ntk);
+            eb.load_b(boff, lane4, nid, ntk);
             const int tk0 = __builtin_amdgcn_readfirstlane(tk);
             const unsigned long long vm = FULL ? ~0ull : (1ull << (ce - i)) - 1ull;
             // node 0: every event enters list 0 with s = its index
@@ -943,10 +952,6 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
             if (m0) {
                 const int q = hd[0];
                 const int c0 = __popcll(m0);
-                // the newest entry overwritten (the oldest ones have lower ticks)
-                if (q + c0 > WAVE &&
-                    __builtin_amdgcn_readlane(rh[0], (q + c0 - 1) & (WAVE - 1)) >= tk0)
-                    rovf = true;
                 // the block's node-0 events in order to scr[0..c0), then to
                 // ring slots q, q+1, ... (other lanes write scr[WAVE], unread)
                 const int rank = __builtin_amdgcn_mbcnt_hi(
@@ -956,6 +961,7 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                 const int r = (lane - q) & (WAVE - 1);
                 const bool take = r < c0;
                 const int2 e = scr[take ? r : WAVE];
+                ovr |= (take & (rh[0] >= tk0)) ? 1 : 0;
                 rl[0] = take ? e.x + uh.lo[0] + 1 : rl[0];
                 rh[0] = take ? e.x + uh.hi[0] : rh[0];
                 rs[0] = take ? e.y : rs[0];
@@ -971,7 +977,7 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                 if (nh[k - 1] < tk0) continue;
                 unsigned long long pk = __builtin_amdgcn_ballot_w64(id == u.ty[k]);
                 if (!FULL) pk &= vm;
-                const int base = hd[k - 1] >= WAVE ? hd[k - 1] - 1 : -1;
+                const int base = hd[k - 1] - 1;
                 while (pk) {
                     const int x = (int)__builtin_ctzll(pk);
                     pk ^= 1ull << x;
@@ -984,10 +990,8 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                     if (__builtin_amdgcn_readlane(rh[k - 1], q) < t) continue;
                     const int s = __builtin_amdgcn_readlane(rs[k - 1], q);
                     if (k < N - 2) {
-                        const int qk = hd[k] & (WAVE - 1);
-                        if (hd[k] >= WAVE && __builtin_amdgcn_readlane(rh[k], qk) >= tk0)
-                            rovf = true;
-                        const bool at = lane == qk;
+                        const bool at = lane == (hd[k] & (WAVE - 1));
+                        ovr |= (at & (rh[k] >= tk0)) ? 1 : 0;
                         rl[k] = at ? t + uh.lo[k] + 1 : rl[k];
                         rh[k] = at ? t + uh.hi[k] : rh[k];
                         rs[k] = at ? s : rs[k];
@@ -1059,13 +1063,13 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                 remb &= rb1;
             }
         };
-        int i = cb;
-        for (; i + WAVE <= ce; i += WAVE) block(std::true_type(), i);
-        if (i < ce) block(std::false_type(), i);
+        int i = cb, boff = 4 * WAVE;  // (boff: byte offset of the next block)
+        for (; i + WAVE <= ce; i += WAVE, boff += 4 * WAVE) block(std::true_type(), i, boff);
+        if (i < ce) block(std::false_type(), i, boff);
     }
     w.flush(status);
     cnt_out = cnt;
-    return !rovf;
+    return __builtin_amdgcn_ballot_w64(ovr != 0) == 0;
 }
 
 // Everything one work item (a tile of 64 candidates over segment p of P)
