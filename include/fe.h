@@ -119,7 +119,9 @@ typedef enum fe_param {
                                 taken when the sampled survivor fraction s
                                 satisfies s < 1 - FE_PARAM_PASS1_COST/1000
                                 (then the relaxed pass costs less than it
-                                saves), else one.  The frequent episodes and
+                                saves), else one; with FE_PARAM_PASS1_COST
+                                >= 1000 no sample is taken and such levels
+                                take one pass.  The frequent episodes and
                                 exact counts are the same either way.          */
     FE_PARAM_HOST_TILING = 9, /* fe_mine: 0 (default) = each level's
                                 candidates are pruned and tiled on the device
@@ -138,9 +140,11 @@ typedef enum fe_param {
     FE_PARAM_CROSSOVER_B_RELAXED = 12, /* relaxed counter (Algorithm 3);
                                 defaults 9232 and 5798 (same fit)             */
     FE_PARAM_PASS1_COST = 13, /* cost of the relaxed pass per candidate, in
-                                thousandths of the exact pass's (default 800,
-                                measured on the mining workload's levels 3
-                                and 4); used by FE_PARAM_ELIMINATION = 2      */
+                                thousandths of the exact pass's (default
+                                1000: on the mining workload's level 4 the
+                                relaxed pass takes as long as the exact one
+                                with shared lists); used by
+                                FE_PARAM_ELIMINATION = 2                      */
     FE_PARAM_SAMPLE_MIN = 14, /* smallest level sampled by FE_PARAM_ELIMINATION
                                 = 2 (default 131072 candidates)                */
     FE_PARAM_SHARED_LISTS = 15 /* 1 (default) = exact whole-stream counting of

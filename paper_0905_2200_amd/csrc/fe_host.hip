@@ -109,7 +109,7 @@ struct fe_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
-    int64_t param[NPARAM] = {0, 4096, 1024, 1, 0, 1, -8136, 19504, 2, 0, 0, 9232, 5798, 800,
+    int64_t param[NPARAM] = {0, 4096, 1024, 1, 0, 1, -8136, 19504, 2, 0, 0, 9232, 5798, 1000,
                              131072, 1};
     fe_stats stats{};
     // workspace
@@ -1266,12 +1266,16 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
         int64_t smp_n = 0, smp_kept = 0;
         if (emode == 2 && !htile && (int64_t)M >= c->param[FE_PARAM_SAMPLE_MIN]) {
             // two passes pay when the relaxed pass (cost r per candidate,
-            // relative to the exact one) prunes more than r of the level
-            if ((rc = sample_survival(c, ids, ticks, si, level, (int64_t)M, wbound, bbound, theta,
-                                      smp_n, smp_kept)))
-                return rc;
+            // relative to the exact one) prunes more than r of the level;
+            // with r >= 1 nothing can, and no sample is taken
             const double r = (double)c->param[FE_PARAM_PASS1_COST] / 1000.0;
-            elim = (double)smp_kept < (1.0 - r) * (double)smp_n;
+            elim = false;
+            if (r < 1.0) {
+                if ((rc = sample_survival(c, ids, ticks, si, level, (int64_t)M, wbound, bbound,
+                                          theta, smp_n, smp_kept)))
+                    return rc;
+                elim = (double)smp_kept < (1.0 - r) * (double)smp_n;
+            }
         }
         int64_t kept = 0;  // candidates of the exact pass (device tiling)
         if (!htile) {

@@ -240,17 +240,22 @@ def test_one_pass_mining_same_result(ctx, fe):
                 assert np.array_equal(a["upper"], b["upper"]) and \
                     a["n_survivors"] == b["n_survivors"], (key, a["level"])
     # the rule: two passes when the sampled survivor fraction is below
-    # 1 - cost; levels below the sampling size take two passes
+    # 1 - cost (no sample and one pass when cost >= 1); levels below the
+    # sampling size take two passes
     for key, cost in (("rule_two", 0), ("rule_one", 1000), ("rule", 800)):
         big = [L for L in res[key] if L["level"] >= 2 and L["n_candidates"] >= 1000]
-        assert big and all(L["sample_n"] > 0 for L in big), key
+        assert big, key
         for L in res[key]:
             if L["level"] < 2:
                 continue
-            if L["sample_n"]:
-                want = 2 if L["sample_kept"] < (1 - cost / 1000) * L["sample_n"] else 1
-            else:
+            if L["n_candidates"] < 1000:
                 want = 2
+            elif cost >= 1000:
+                assert L["sample_n"] == 0, (key, L["level"])
+                want = 1
+            else:
+                assert L["sample_n"] > 0, (key, L["level"])
+                want = 2 if L["sample_kept"] < (1 - cost / 1000) * L["sample_n"] else 1
             assert L["passes"] == want, (key, L["level"])
     assert any(L["passes"] == 2 for L in res["rule_two"] if L["sample_n"])
     assert all(L["passes"] == 1 for L in res["one"] if L["level"] >= 2)
