@@ -8,8 +8,8 @@ size penalty f(N) of Eq. 2; the paper's Table 1 and its a/N + b fit, Sec. 6.2).
 prints one JSON line: the measured table and the fitted (a, b) for the
 exact and relaxed counters.  The library's defaults for
 FE_PARAM_CROSSOVER_A / _B come from this measurement on an MI355X.
-Candidates are tiles of join siblings (shared first N-1 types) over the
-mining recording, as level-wise mining produces them."""
+Candidates are tiles of join siblings (shared first N-1 types and first
+N-2 hops) over the mining recording, as level-wise mining produces them."""
 import argparse
 import json
 import sys
@@ -19,13 +19,18 @@ import numpy as np
 
 
 def sibling_tiles(rng, tiles, N, num_types, intervals):
-    """tiles x 64 candidates; each tile shares its first N-1 types."""
+    """tiles x 64 candidates; each tile shares its first N-1 types and its
+    first N-2 hops (the join siblings of one episode), each lane draws its
+    last type and last hop."""
     M = tiles * 64
     pre = rng.integers(0, num_types, size=(tiles, max(N - 1, 1)))
     types = np.empty((M, N), np.int32)
     types[:, :N - 1] = np.repeat(pre[:, :N - 1], 64, axis=0)
     types[:, N - 1] = rng.integers(0, num_types, size=M)
     k = rng.integers(0, len(intervals), size=(M, max(N - 1, 1)))[:, :N - 1]
+    if N >= 3:
+        kt = rng.integers(0, len(intervals), size=(tiles, N - 2))
+        k[:, :N - 2] = np.repeat(kt, 64, axis=0)
     lo = np.array([a for a, _ in intervals], np.int32)[k]
     hi = np.array([b for _, b in intervals], np.int32)[k]
     return {"types": types, "len": np.full(M, N, np.int32), "lo": np.ascontiguousarray(lo),
