@@ -937,12 +937,13 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
     for (int cb = 0; cb < n; cb += EV_CHUNK) {
         const int ce = n - cb > EV_CHUNK ? cb + EV_CHUNK : n;
         const EvBuf eb(ids, ticks, cb, ce);
-        int nid, ntk;
-        eb.load(0, lane4, nid, ntk);
-        // (full blocks and the final partial one are separate copies)
-        auto block = [&](auto full_tag, int i, int boff) {
+        int ia, ta, ib, tb;  // two blocks in flight: this one and the prefetched next
+        eb.load(0, lane4, ia, ta);
+        // (full blocks and the final partial one are separate copies; full
+        // blocks alternate the registers of the current and next block)
+        auto block = [&](auto full_tag, int i, int boff, const int id, const int tk, int &nid,
+                         int &ntk) {
             constexpr bool FULL = decltype(full_tag)::value;
-            const int id = nid, tk = ntk;
             eb.load_b(boff, lane4, nid, ntk);
             const int tk0 = __builtin_amdgcn_readfirstlane(tk);
             const unsigned long long vm = FULL ? ~0ull : (1ull << (ce - i)) - 1ull;
@@ -1064,8 +1065,18 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
             }
         };
         int i = cb, boff = 4 * WAVE;  // (boff: byte offset of the next block)
-        for (; i + WAVE <= ce; i += WAVE, boff += 4 * WAVE) block(std::true_type(), i, boff);
-        if (i < ce) block(std::false_type(), i, boff);
+        for (; i + 2 * WAVE <= ce; i += 2 * WAVE, boff += 8 * WAVE) {
+            block(std::true_type(), i, boff, ia, ta, ib, tb);
+            block(std::true_type(), i + WAVE, boff + 4 * WAVE, ib, tb, ia, ta);
+        }
+        if (i + WAVE <= ce) {
+            block(std::true_type(), i, boff, ia, ta, ib, tb);
+            i += WAVE;
+            boff += 4 * WAVE;
+            ia = ib;
+            ta = tb;
+        }
+        if (i < ce) block(std::false_type(), i, boff, ia, ta, ib, tb);
     }
     w.flush(status);
     cnt_out = cnt;
