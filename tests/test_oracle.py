@@ -77,7 +77,7 @@ def test_random_tiny_streams():
     rng = np.random.default_rng(2024)
     eps = _all_episodes(3, 2, [(0, 2), (1, 4)]) + _all_episodes(3, 3, [(0, 3), (1, 4)])[::3] \
         + _all_episodes(2, 4, [(0, 3), (1, 5)])[::5]
-    for trial in range(400):
+    for trial in range(4000):
         n = int(rng.integers(0, 15))
         ids, ticks = synth.tiny_stream(rng, n, 3, 3)
         ex = _counts(ids, ticks, eps, EXACT, 3)
@@ -91,7 +91,7 @@ def test_random_tiny_streams():
 def test_random_tiny_streams_many_seeds():
     rng = np.random.default_rng(99)
     eps = _all_episodes(3, 2, [(0, 2), (1, 4)]) + _all_episodes(3, 3, [(0, 3), (2, 5)])
-    for trial in range(20000):
+    for trial in range(100_000):
         ids, ticks = synth.tiny_stream(rng, int(rng.integers(0, 13)), 3, 4)
         ex = _counts(ids, ticks, eps, EXACT, 3)
         rx = _counts(ids, ticks, eps, RELAXED, 3)
