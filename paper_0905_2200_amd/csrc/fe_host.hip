@@ -1398,7 +1398,13 @@ extern "C" int fe_mine(fe_ctx *c, const int32_t *ids, const int32_t *ticks, int6
             for (int i = 0; i < nf; ++i)
                 std::memcpy(NF.key.data() + (size_t)i * wk, C.at(fsel[i]), wk * sizeof(int));
         }
-        sort_episodes(NF, &fup, &fex);
+        {
+            HTimer ht(c, "host_sort");
+            // (the join writes candidates in key order; the compaction that
+            // found the frequent ones does not keep it)
+            if (djoin) order_by_index(NF, fsel, (int64_t)M, &fup, &fex);
+            else sort_episodes(NF, &fup, &fex);
+        }
         Lv.level = level;
         Lv.ncand = (int64_t)M;
         Lv.nsurv = cnts[1];

@@ -109,6 +109,36 @@ template <class IV> void sort_episodes(EpisodesT<IV> &E, std::vector<int> *vals_
     if (vals_b) vals_b->swap(b2);
 }
 
+// Reorder E's entries, given in the order of their candidate indices sel
+// (distinct, below M), into increasing index order, and the values with
+// them: when the candidates were generated in key order this sorts E in
+// O(M/64 + F) -- the rank of an index is found in a bitmap of the selected
+// indices with per-word prefix counts.
+template <class IV>
+void order_by_index(EpisodesT<IV> &E, const std::vector<int> &sel, int64_t M,
+                    std::vector<int> *vals_a, std::vector<int> *vals_b)
+{
+    const int w = 3 * E.m - 2;
+    const size_t F = E.count();
+    std::vector<uint64_t> bm((size_t)((M + 63) / 64), 0);
+    for (size_t k = 0; k < F; ++k) bm[(size_t)sel[k] >> 6] |= 1ull << (sel[k] & 63);
+    std::vector<int64_t> pre(bm.size() + 1, 0);
+    for (size_t j = 0; j < bm.size(); ++j) pre[j + 1] = pre[j] + __builtin_popcountll(bm[j]);
+    IV k2(E.key.size());
+    std::vector<int> a2(vals_a ? F : 0), b2(vals_b ? F : 0);
+    for (size_t k = 0; k < F; ++k) {
+        const int x = sel[k];
+        const size_t d = (size_t)(pre[(size_t)x >> 6] +
+                                  __builtin_popcountll(bm[(size_t)x >> 6] & ((1ull << (x & 63)) - 1ull)));
+        std::memcpy(k2.data() + d * w, E.at(k), w * sizeof(int));
+        if (vals_a) a2[d] = (*vals_a)[k];
+        if (vals_b) b2[d] = (*vals_b)[k];
+    }
+    E.key.swap(k2);
+    if (vals_a) vals_a->swap(a2);
+    if (vals_b) vals_b->swap(b2);
+}
+
 // Level 2: every ordered pair of frequent types (repeats allowed) times
 // every interval of I.
 template <class IV>

@@ -108,6 +108,31 @@ static void check_sort(std::mt19937 &g)
     }
 }
 
+static void check_order_by_index(std::mt19937 &g)
+{
+    for (int trial = 0; trial < 30; ++trial) {
+        const int m = 1 + trial % 5;
+        EpisodesT<IV> E = random_set(g, m, 4, 50, 3);  // sorted, distinct
+        const size_t F = E.count(), w = 3 * m - 2;
+        // E's entries are candidates 3i + (i % 2) of a larger, key-ordered
+        // set; they arrive in shuffled order with their indices
+        std::vector<size_t> p(F);
+        for (size_t i = 0; i < F; ++i) p[i] = i;
+        std::shuffle(p.begin(), p.end(), g);
+        EpisodesT<IV> S;
+        S.m = m;
+        std::vector<int> sel, va;
+        for (size_t i : p) {
+            S.key.insert(S.key.end(), E.at(i), E.at(i) + w);
+            sel.push_back((int)(3 * i + i % 2));
+            va.push_back((int)i);
+        }
+        order_by_index(S, sel, (int64_t)(3 * F + 2), &va, nullptr);
+        CHECK(S.key == E.key);
+        for (size_t i = 0; i < F; ++i) CHECK(va[i] == (int)i);
+    }
+}
+
 static void check_pack(std::mt19937 &g)
 {
     for (int trial = 0; trial < 40; ++trial) {
@@ -182,6 +207,7 @@ int main()
     std::mt19937 g(12345);
     check_join(g);
     check_sort(g);
+    check_order_by_index(g);
     check_pack(g);
     if (fails) {
         std::fprintf(stderr, "%d checks failed\n", fails);
