@@ -1004,8 +1004,8 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                     }
                 }
             }
-            if (remb == 0)
-                if (lm < tk0) return;
+            // (one scalar test: remb, or 1 while some lane's list passes)
+            if ((remb | (unsigned long long)(unsigned)(lm >= tk0)) == 0) return;
             // type table of the block for the last node's search
             tm[lane] = 0;
             evs[lane] = make_int2(id, tk);
