@@ -84,7 +84,9 @@ typedef enum fe_mode {
 /* Tunables for fe_set_param. */
 typedef enum fe_param {
     FE_PARAM_SEGMENTS = 0,   /* MapConcatenate segment count P; 0 = automatic  */
-    FE_PARAM_TARGET_WAVES = 1, /* waves the automatic P aims for per launch    */
+    FE_PARAM_TARGET_WAVES = 1, /* waves the automatic P aims for per launch
+                                (default 16384: two generations of 8 waves
+                                per SIMD on 256 CUs)                          */
     FE_PARAM_MIN_SEG_EVENTS = 2, /* smallest segment the automatic P allows   */
     FE_PARAM_CONCAT_TREE = 3, /* 1 = wave-shuffle tree Concatenate when P >= 16,
                                  0 = per-candidate sequential walk             */
@@ -102,7 +104,7 @@ typedef enum fe_param {
     FE_PARAM_CROSSOVER_B = 7, /* counter: a group of tiles >= A/N + B tiles of
                                 N-node candidates is counted whole-stream
                                 (P = 1), a smaller one by MapConcatenate with
-                                P >= 2.  Defaults 9493 and 12985 (A may be
+                                P >= 2.  Defaults 8472 and 13112 (A may be
                                 negative): the least-squares fit to crossovers
                                 measured on a 256-CU MI355X (python -m
                                 paper_0905_2200_amd.crossover).  Ignored when
@@ -138,7 +140,7 @@ typedef enum fe_param {
                                 episodes only                                  */
     FE_PARAM_CROSSOVER_A_RELAXED = 11, /* the hybrid rule's A and B for the  */
     FE_PARAM_CROSSOVER_B_RELAXED = 12, /* relaxed counter (Algorithm 3);
-                                defaults 9240 and 6411 (same fit)             */
+                                defaults 9699 and 6165 (same fit)             */
     FE_PARAM_PASS1_COST = 13, /* cost of the relaxed pass per candidate, in
                                 thousandths of the exact pass's (default
                                 1000: on the mining workload's level 4 the

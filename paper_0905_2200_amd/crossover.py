@@ -50,17 +50,18 @@ def timed(ctx, torch, fn, reps):
 
 
 def crossover_tiles(tiles, ratio):
-    """Smallest tile count where P = 1 is at least as fast (ratio = t(P=1) /
-    t(best P>1) <= 1), interpolated in log2(tiles); None if never."""
-    for j, r in enumerate(ratio):
-        if r <= 1.0:
-            if j == 0:
-                return float(tiles[0])
-            x0, x1 = np.log2(tiles[j - 1]), np.log2(tiles[j])
-            r0, r1 = np.log(ratio[j - 1]), np.log(r)
-            x = x0 + (x1 - x0) * (r0 / (r0 - r1))
-            return float(2.0 ** x)
-    return None
+    """Tile count from which on P = 1 stays at least as fast (ratio = t(P=1)
+    / t(best P>1) <= 1 at it and every larger size), interpolated in
+    log2(tiles) after the last size where segmenting wins; None if never."""
+    last = max((j for j, r in enumerate(ratio) if r > 1.0), default=-1)
+    if last == len(ratio) - 1:
+        return None
+    if last < 0:
+        return float(tiles[0])
+    x0, x1 = np.log2(tiles[last]), np.log2(tiles[last + 1])
+    r0, r1 = np.log(ratio[last]), np.log(ratio[last + 1])
+    x = x0 + (x1 - x0) * (r0 / (r0 - r1)) if r0 != r1 else x1
+    return float(2.0 ** x)
 
 
 def fit_a_over_n_plus_b(Ns, C):
@@ -82,7 +83,9 @@ def main(argv=None):
     rng = np.random.default_rng(99)
     Ns = [2, 3, 4] if args.quick else [2, 3, 4, 5, 6, 7, 8]
     tiles = [256, 1024, 4096] if args.quick else [512, 1024, 2048, 4096, 8192, 16384, 32768]
-    out = {"n_events": int(s["ids"].size), "tiles": tiles, "table": {}, "fit": {}}
+    target = ctx.get_param(fe.PARAM_TARGET_WAVES)  # the automatic P's aim
+    out = {"n_events": int(s["ids"].size), "tiles": tiles, "target_waves": target,
+           "table": {}, "fit": {}}
     for mode, name in ((fe.FE_EXACT, "exact"), (fe.FE_RELAXED, "relaxed")):
         cross = []
         for N in Ns:
@@ -95,7 +98,7 @@ def main(argv=None):
                     return timed(ctx, torch, lambda: ctx.count(ids, ticks, s["num_types"], cand,
                                                                mode), args.reps)
                 t1 = run(1)
-                base = max(2, -(-4096 // t))
+                base = max(2, -(-target // t))
                 tp = min(run(P) for P in sorted({max(2, base // 2), base, 2 * base}))
                 ratios.append(t1 / tp)
                 print("%s N=%d tiles=%d: P=1 %.2f ms, best P>1 %.2f ms" % (

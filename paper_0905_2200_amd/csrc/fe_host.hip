@@ -109,7 +109,7 @@ struct fe_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
-    int64_t param[NPARAM] = {0, 4096, 1024, 1, 0, 1, 9493, 12985, 2, 0, 0, 9240, 6411, 1000,
+    int64_t param[NPARAM] = {0, 16384, 1024, 1, 0, 1, 8472, 13112, 2, 0, 0, 9699, 6165, 1000,
                              131072, 1};
     fe_stats stats{};
     // workspace
