@@ -5,8 +5,10 @@ counts (P = 1) equal the CPU oracle's bit for bit and the per-candidate
 lists' counts, for N = 3..8; with repeated types in the shared prefix and
 last types equal to a shared type; with ties in the ticks; with type ids
 above 63 (hash collisions in the last node's table); with bursts that
-overflow the 64-entry rings (the tile is then counted the general way); and
-on tiny, ragged and empty streams."""
+overflow the 64-entry rings (the tile is then counted the general way); on
+tiny, ragged and empty streams; and for runs of siblings over several tiles
+(whole tiles, a padded remainder tile, remainders packed with other runs'
+into mixed tiles)."""
 import numpy as np
 import pytest
 
@@ -44,16 +46,16 @@ def _count(ctx, fe, ids, ticks, num_types, cand, shared):
         ctx.set_param(fe.PARAM_SHARED_LISTS, 1)
 
 
-def _siblings(rng, N, runs, num_types, repeat=False, last_pool=None):
-    """runs x 64 candidates; each run shares N-1 node types and N-2 hops,
-    each lane draws its last type and last hop."""
+def _siblings(rng, N, runs, num_types, repeat=False, last_pool=None, sizes=None):
+    """runs x 64 candidates (or runs of the given sizes); each run shares N-1
+    node types and N-2 hops, each lane draws its last type and last hop."""
     eps = []
-    for _ in range(runs):
+    for r in range(runs if sizes is None else len(sizes)):
         pre = [int(x) for x in rng.integers(0, num_types, N - 1)]
         if repeat and N >= 3:  # a type repeated inside the shared prefix
             pre[1] = pre[0]
         hops = [PRE_HOPS[int(rng.integers(len(PRE_HOPS)))] for _ in range(N - 2)]
-        for _ in range(64):
+        for _ in range(64 if sizes is None else sizes[r]):
             if last_pool is None:
                 last = int(rng.integers(num_types))
             else:
@@ -157,3 +159,18 @@ def test_tiny_and_ragged(ctx, fe, n):
     ids_h, ticks_h = _stream(rng, n, 3, mean_gap=20)
     cand = _siblings(rng, 3, 2, 3)
     _check(ctx, fe, ids_h, ticks_h, 3, cand, "n=%d" % n, nonvacuous=n >= 1000)
+
+
+# runs over 2, 3 and 17 tiles (a remainder of at least 32 gets a padded tile
+# of its own, a shorter one is packed with others), one of 64 and short ones
+RUN_SIZES = [100, 64, 130, 65 + 32, 200, 20, 64 * 17 + 40, 128, 7, 64 * 3]
+
+
+@pytest.mark.parametrize("N", [3, 4, 6])
+def test_sibling_runs_over_several_tiles(ctx, fe, N):
+    rng = np.random.default_rng(900 + N)
+    nt = 6 if N <= 4 else 4
+    ids_h, ticks_h = _stream(rng, 20_000, nt, mean_gap=8 if N <= 4 else 3)
+    cand = _siblings(rng, N, 0, nt, sizes=RUN_SIZES)
+    banner("sibling runs over several tiles: N=%d, %d candidates" % (N, cand["M"]))
+    _check(ctx, fe, ids_h, ticks_h, nt, cand, "runs N=%d" % N)
