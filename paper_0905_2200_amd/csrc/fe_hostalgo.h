@@ -126,14 +126,18 @@ void order_by_index(EpisodesT<IV> &E, const std::vector<int> &sel, int64_t M,
     for (size_t j = 0; j < bm.size(); ++j) pre[j + 1] = pre[j] + __builtin_popcountll(bm[j]);
     IV k2(E.key.size());
     std::vector<int> a2(vals_a ? F : 0), b2(vals_b ? F : 0);
-    for (size_t k = 0; k < F; ++k) {
-        const int x = sel[k];
-        const size_t d = (size_t)(pre[(size_t)x >> 6] +
-                                  __builtin_popcountll(bm[(size_t)x >> 6] & ((1ull << (x & 63)) - 1ull)));
-        std::memcpy(k2.data() + d * w, E.at(k), w * sizeof(int));
-        if (vals_a) a2[d] = (*vals_a)[k];
-        if (vals_b) b2[d] = (*vals_b)[k];
-    }
+    // (distinct destinations: the scatter runs on every host thread)
+    par_for((int64_t)F, 65536, [&](int64_t b, int64_t e, int) {
+        for (int64_t k = b; k < e; ++k) {
+            const int x = sel[k];
+            const size_t d = (size_t)(pre[(size_t)x >> 6] +
+                                      __builtin_popcountll(bm[(size_t)x >> 6] &
+                                                           ((1ull << (x & 63)) - 1ull)));
+            std::memcpy(k2.data() + d * w, E.at(k), w * sizeof(int));
+            if (vals_a) a2[d] = (*vals_a)[k];
+            if (vals_b) b2[d] = (*vals_b)[k];
+        }
+    });
     E.key.swap(k2);
     if (vals_a) vals_a->swap(a2);
     if (vals_b) vals_b->swap(b2);
@@ -172,27 +176,30 @@ int64_t gen_join_plan(const EpisodesT<IV> &F, std::vector<int64_t> &first, std::
     const int64_t cnt = (int64_t)F.count();
     first.assign(cnt, 0);
     off.assign(cnt + 1, 0);
+    // F is sorted, so equal prefixes (first m-1 nodes and hops) are runs:
+    // their starts, and the distinct prefixes packed for the searches
+    IV starts;
+    par_select(cnt, [&](int64_t i) {
+        return i == 0 || !std::equal(F.at(i - 1), F.at(i - 1) + ov, F.at(i));
+    }, starts);
+    const int64_t U = (int64_t)starts.size();
+    std::vector<int> up((size_t)U * ov);
+    for (int64_t q = 0; q < U; ++q) std::memcpy(up.data() + q * ov, F.at(starts[q]), ov * sizeof(int));
     par_for(cnt, 4096, [&](int64_t b, int64_t e, int) {
         for (int64_t a = b; a < e; ++a) {
             const int *suf = F.at(a) + 3;
-            int64_t lo = 0, hi = cnt;  // first beta whose prefix is >= suf
+            int64_t lo = 0, hi = U;  // first distinct prefix >= suf
             while (lo < hi) {
                 const int64_t mid = (lo + hi) >> 1;
-                if (std::lexicographical_compare(F.at(mid), F.at(mid) + ov, suf, suf + ov))
+                const int *pm = up.data() + mid * ov;
+                if (std::lexicographical_compare(pm, pm + ov, suf, suf + ov))
                     lo = mid + 1;
                 else
                     hi = mid;
             }
-            int64_t l2 = lo, h2 = cnt;  // first beta whose prefix is > suf
-            while (l2 < h2) {
-                const int64_t mid = (l2 + h2) >> 1;
-                if (!std::lexicographical_compare(suf, suf + ov, F.at(mid), F.at(mid) + ov))
-                    l2 = mid + 1;
-                else
-                    h2 = mid;
-            }
-            first[a] = lo;
-            off[a + 1] = l2 - lo;
+            const bool hit = lo < U && std::equal(suf, suf + ov, up.data() + lo * ov);
+            first[a] = lo < U ? starts[lo] : cnt;
+            off[a + 1] = hit ? (lo + 1 < U ? starts[lo + 1] : cnt) - starts[lo] : 0;
         }
     });
     for (int64_t a = 0; a < cnt; ++a) off[a + 1] += off[a];
