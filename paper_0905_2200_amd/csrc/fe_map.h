@@ -885,8 +885,9 @@ __device__ __forceinline__ bool shared_hops(const Cand<N> &c, bool valid, UHops<
 //   Lists 0..N-3 are rings of the 64 newest entries held across the lanes
 // of three registers (lane q: slot q), oldest to newest from the next slot
 // to write; an entry is kept as the first and last tick its hop test passes
-// at (tick + lo + 1, tick + hi) with its s, unused slots first passing at
-// EMPTY.  Ticks do not decrease along a ring, so the entries that pass from
+// at (tick + lo + 1, tick + hi) with its s; a ring starts full of unused
+// slots that pass from GONE to GONE (in every search's count, never at a
+// tick).  Ticks do not decrease along a ring, so the entries that pass from
 // a tick t on or earlier are its first c slots in that order (c: a
 // ballot's popcount), and the newest of them passes at t iff its last
 // passing tick is at least t.  Overwriting an entry that could still pass a
