@@ -938,10 +938,12 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
     for (int cb = 0; cb < n; cb += EV_CHUNK) {
         const int ce = n - cb > EV_CHUNK ? cb + EV_CHUNK : n;
         const EvBuf eb(ids, ticks, cb, ce);
-        int ia, ta, ib, tb;  // two blocks in flight: this one and the prefetched next
+        int ia, ta, ib, tb, ic, tc;  // this block and the next two, in flight
         eb.load(0, lane4, ia, ta);
+        eb.load(WAVE, lane4, ib, tb);
         // (full blocks and the final partial one are separate copies; full
-        // blocks alternate the registers of the current and next block)
+        // blocks rotate three register sets, so each block's loads are
+        // issued two blocks ahead)
         auto block = [&](auto full_tag, int i, int boff, const int id, const int tk, int &nid,
                          int &ntk) {
             constexpr bool FULL = decltype(full_tag)::value;
@@ -1065,19 +1067,25 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                 remb &= rb1;
             }
         };
-        int i = cb, boff = 4 * WAVE;  // (boff: byte offset of the next block)
-        for (; i + 2 * WAVE <= ce; i += 2 * WAVE, boff += 8 * WAVE) {
-            block(std::true_type(), i, boff, ia, ta, ib, tb);
+        int i = cb, boff = 8 * WAVE;  // (boff: byte offset of the block after the next)
+        for (; i + 3 * WAVE <= ce; i += 3 * WAVE, boff += 12 * WAVE) {
+            block(std::true_type(), i, boff, ia, ta, ic, tc);
             block(std::true_type(), i + WAVE, boff + 4 * WAVE, ib, tb, ia, ta);
+            block(std::true_type(), i + 2 * WAVE, boff + 8 * WAVE, ic, tc, ib, tb);
         }
-        if (i + WAVE <= ce) {
-            block(std::true_type(), i, boff, ia, ta, ib, tb);
-            i += WAVE;
-            boff += 4 * WAVE;
-            ia = ib;
-            ta = tb;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            if (i + WAVE <= ce) {
+                block(std::true_type(), i, boff, ia, ta, ic, tc);
+                i += WAVE;
+                boff += 4 * WAVE;
+                ia = ib;
+                ta = tb;
+                ib = ic;
+                tb = tc;
+            }
         }
-        if (i < ce) block(std::false_type(), i, boff, ia, ta, ib, tb);
+        if (i < ce) block(std::false_type(), i, boff, ia, ta, ic, tc);
     }
     w.flush(status);
     cnt_out = cnt;
