@@ -935,6 +935,9 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
     // still pass a later test (the results are then discarded; every index
     // stays within the rings)
     int ovr = 0;
+    // s of the block's list N-2 entries, in the lanes of their events (read
+    // only at positions entered in the same block)
+    int sv = 0;
     for (int cb = 0; cb < n; cb += EV_CHUNK) {
         const int ce = n - cb > EV_CHUNK ? cb + EV_CHUNK : n;
         const EvBuf eb(ids, ticks, cb, ce);
@@ -962,18 +965,21 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                     (unsigned)(m0 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m0, 0u));
                 scr[is0 ? rank : WAVE] = make_int2(tk, i + lane);
                 __builtin_amdgcn_wave_barrier();
+                // (slots r >= c0 read a stale entry and keep their own; the
+                // empty asm keeps the read whole rather than predicated)
                 const int r = (lane - q) & (WAVE - 1);
                 const bool take = r < c0;
-                const int2 e = scr[take ? r : WAVE];
+                unsigned long long e = __builtin_bit_cast(unsigned long long, scr[r]);
+                asm volatile("" : "+v"(e));
+                const int et = (int)(unsigned)e, es = (int)(unsigned)(e >> 32);
                 ovr |= (take & (rh[0] >= tk0)) ? 1 : 0;
-                rl[0] = take ? e.x + uh.lo[0] + 1 : rl[0];
-                rh[0] = take ? e.x + uh.hi[0] : rh[0];
-                rs[0] = take ? e.y : rs[0];
+                rl[0] = take ? et + uh.lo[0] + 1 : rl[0];
+                rh[0] = take ? et + uh.hi[0] : rh[0];
+                rs[0] = take ? es : rs[0];
                 hd[0] = q + c0;
                 nh[0] = __builtin_amdgcn_readlane(tk, 63 - __clzll(m0)) + uh.hi[0];
             }
             unsigned long long remb = 0;
-            int sv = 0;
 #pragma unroll
             for (int k = 1; k <= N - 2; ++k) {
                 // (skipped when no entry of list k-1 can lie in range of the
@@ -1007,8 +1013,12 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                     }
                 }
             }
-            // (one scalar test: remb, or 1 while some lane's list passes)
-            if ((remb | (unsigned long long)(unsigned)(lm >= tk0)) == 0) return;
+            // (one scalar test: remb, or a nonzero mask while some lane's list
+            // passes a tick of the block: lm >= tk0 iff some lane's tick is at
+            // most lm, as in a full block every tick is at least tk0; lanes past
+            // the end of a partial block read tick 0, which at worst sends that
+            // one block on to an empty search)
+            if ((remb | __builtin_amdgcn_ballot_w64(tk <= lm)) == 0) return;
             // type table of the block for the last node's search
             tm[lane] = 0;
             evs[lane] = make_int2(id, tk);
