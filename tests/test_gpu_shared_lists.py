@@ -174,3 +174,32 @@ def test_sibling_runs_over_several_tiles(ctx, fe, N):
     cand = _siblings(rng, N, 0, nt, sizes=RUN_SIZES)
     banner("sibling runs over several tiles: N=%d, %d candidates" % (N, cand["M"]))
     _check(ctx, fe, ids_h, ticks_h, nt, cand, "runs N=%d" % N)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_sibling_runs(ctx, fe, seed):
+    """Random N (3..6), hops (some with lo > 0 and narrow windows), run
+    sizes, stream lengths (not multiples of 64) and burstiness; shared
+    lists on and off against the oracle."""
+    rng = np.random.default_rng(1000 + seed)
+    N = int(rng.integers(3, 7))
+    nt = int(rng.integers(3, 9))
+    n = int(rng.integers(2_000, 12_000))
+    gaps = rng.integers(0, int(rng.integers(2, 16)), n)
+    if seed % 3 == 0:  # bursts: runs of equal ticks
+        gaps[rng.random(n) < 0.5] = 0
+    ids_h = rng.integers(0, nt, n).astype(np.int32)
+    ticks_h = np.cumsum(gaps).astype(np.int32)
+    hop_pool = [(0, 5), (0, 30), (10, 40), (50, 100), (5, 8), (20, 25)]
+    eps = []
+    for _ in range(int(rng.integers(2, 6))):
+        pre = [int(x) for x in rng.integers(0, nt, N - 1)]
+        hops = [hop_pool[int(rng.integers(len(hop_pool)))] for _ in range(N - 2)]
+        for _ in range(int(rng.integers(20, 150))):
+            lh = hop_pool[int(rng.integers(len(hop_pool)))]
+            iv = hops + [lh]
+            eps.append((tuple(pre) + (int(rng.integers(nt)),), tuple(a for a, _ in iv),
+                        tuple(b for _, b in iv)))
+    cand = synth.pack(eps)
+    banner("random sibling runs: seed=%d N=%d n=%d M=%d" % (seed, N, n, cand["M"]))
+    _check(ctx, fe, ids_h, ticks_h, nt, cand, "seed=%d" % seed, nonvacuous=False)
