@@ -985,7 +985,10 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                 // (skipped when no entry of list k-1 can lie in range of the
                 // block's events, most blocks)
                 if (nh[k - 1] < tk0) continue;
-                unsigned long long pk = __builtin_amdgcn_ballot_w64(id == u.ty[k]);
+                // (node-k events after the newest entry's last passing tick
+                // cannot pass: every older entry's window ends earlier)
+                unsigned long long pk =
+                    __builtin_amdgcn_ballot_w64((id == u.ty[k]) & (tk <= nh[k - 1]));
                 if (!FULL) pk &= vm;
                 const int base = hd[k - 1] - 1;
                 while (pk) {
