@@ -987,8 +987,8 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                 if (nh[k - 1] < tk0) continue;
                 // (node-k events after the newest entry's last passing tick
                 // cannot pass: every older entry's window ends earlier)
-                unsigned long long pk =
-                    __builtin_amdgcn_ballot_w64((id == u.ty[k]) & (tk <= nh[k - 1]));
+                unsigned long long pk = __builtin_amdgcn_ballot_w64(id == u.ty[k]) &
+                                        __builtin_amdgcn_ballot_w64(tk <= nh[k - 1]);
                 if (!FULL) pk &= vm;
                 const int base = hd[k - 1] - 1;
                 while (pk) {
