@@ -993,7 +993,9 @@ __device__ bool sparse_u(const int *ids, const int *ticks, int n, const Cand<N> 
                 const int base = hd[k - 1] - 1;
                 while (pk) {
                     const int x = (int)__builtin_ctzll(pk);
-                    pk ^= 1ull << x;
+                    // (clear bit x of the wave-uniform mask in one scalar
+                    // instruction; the compiler's own form takes three)
+                    asm("s_bitset0_b64 %0, %1" : "+s"(pk) : "s"(x));
                     const int t = __builtin_amdgcn_readlane(tk, x);
                     // entries whose test passes from t on or earlier: the first
                     // popcount in ring order
